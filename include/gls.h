@@ -1,0 +1,180 @@
+/*
+ * gls.h -- C-ABI of libgls, the MI355X (gfx950) streamed GWAS GLS solver.
+ *
+ * For every SNP i the library computes (paper Sec. 1.3, Eq. 1)
+ *
+ *     b_i = (X_i^T M^-1 X_i)^-1 X_i^T M^-1 y,   X_i = [X_L | x_R,i] (n x p),
+ *     M   = h2 * Phi + (1 - h2) * I,
+ *
+ * by the Cholesky rewrite (Sec. 2.1, Eq. 2) and the structured algorithm of
+ * Sec. 2.1 (Listing 1): one Cholesky M = L L^T per study, the covariate terms
+ * X~_L = L^-1 X_L, y~ = L^-1 y, r~_T = X~_L^T y~, S_TL = X~_L^T X~_L hoisted
+ * out of the SNP loop, then per block of SNP columns X~_R,b = L^-1 X_R,b
+ * (Sec. 2.2: SNP vectors packed so the solve is one level-3 operation),
+ * the per-SNP products S_BL,i, S_BR,i, r~_B,i and the p x p SPD solve.
+ * Beyond b_i each SNP also gets
+ *     sigma2_i = (y~^T y~ - b_i^T r~_i) / (n - p)   (GLS residual variance),
+ *     v_i      = (S_i^-1)_pp                          (so se_i = sqrt(sigma2_i v_i)),
+ *     status_i = 0 ok, 1 S_i numerically singular (b_i, sigma2_i, v_i = NaN).
+ * S_i counts as singular when its last squared Cholesky pivot is not above
+ * 2^-40 * S_BR,i.
+ *
+ * Conventions
+ *   - Every matrix is column-major FP64.  A SNP block X_R is n x mb with
+ *     leading dimension ld_xr >= n: SNP j's n samples are contiguous (a torch
+ *     (mb, n) row-major tensor is the same memory).  Coefficients b are
+ *     p x mb with ld_b >= p: SNP j's p coefficients are contiguous, ordered
+ *     [covariates..., SNP].
+ *   - Pointers are DEVICE pointers unless the name ends in _host.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - The caller owns every input, output and the workspace.  The library
+ *     never allocates device memory; it only allocates its small handle and
+ *     creates HIP events (freed by gls_destroy).
+ *   - Every call returns a gls_status; no C++ exception crosses the ABI.
+ *     gls_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef GLS_H
+#define GLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gls_ctx* gls_handle;
+
+typedef enum {
+  GLS_OK = 0,
+  GLS_ERR_ARG = -1,       /* bad size, leading dimension, pointer or option      */
+  GLS_ERR_NOT_SPD = -2,   /* M is not SPD; *info = 1-based failing pivot          */
+  GLS_ERR_HIP = -3,       /* a HIP runtime call failed                            */
+  GLS_ERR_WORKSPACE = -4, /* workspace smaller than gls_workspace_bytes, or not
+                             256-byte aligned                                     */
+  GLS_ERR_STATE = -5,     /* call not valid in the handle's state                 */
+  GLS_ERR_RANK = -6       /* X_L rank deficient (S_TL not SPD); *info = 1-based
+                             covariate index                                      */
+} gls_status;
+
+/* Arithmetic of the per-block triangular solve (everything else is FP64). */
+typedef enum {
+  GLS_FP64 = 0,     /* plain FP64 MFMA                                           */
+  GLS_FP32_IR = 1,  /* FP32 MFMA bulk + FP64 residual refinement sweeps          */
+  GLS_FP16_IR = 2,  /* FP16 MFMA (power-of-two column scaling) + FP64 refinement */
+  GLS_BF16_IR = 3   /* BF16 MFMA (power-of-two column scaling) + FP64 refinement */
+} gls_precision;
+
+/* gls_opts.flags: keep Phi and the factor terms needed by the adjoint. */
+#define GLS_KEEP_FOR_GRAD 1u
+
+typedef struct {
+  int32_t precision;      /* gls_precision                                       */
+  int32_t refine_sweeps;  /* 0..4 refinement sweeps (mixed precision only)       */
+  int32_t block_cols;     /* largest mb any later gls_block call will use (>= 1) */
+  uint32_t flags;         /* GLS_KEEP_FOR_GRAD                                   */
+} gls_opts;
+
+/* Device workspace (bytes) a handle with these sizes and options needs.
+ * Returns 0 for invalid arguments (n <= p, p < 1, p > 20, block_cols < 1). */
+size_t gls_workspace_bytes(int64_t n, int32_t p, const gls_opts* opts);
+
+/* Study setup (Sec. 2.1, Listing 1 before the SNP loop; Eq. 2):
+ *   M = h2 Phi + (1 - h2) I, L = chol(M), the inverse factor L^-1 (blocked:
+ *   inverted diagonal blocks and FP64 MFMA updates), X~_L, y~, S_TL, r~_T,
+ *   y~^T y~, and the Cholesky factor of S_TL.
+ * Phi: n x n symmetric (only its lower triangle is read), ld_phi >= n.
+ * XL : n x (p-1) fixed covariates, ld_xl >= n (may be NULL when p == 1).
+ * y  : n phenotype values.
+ * workspace: device buffer of at least gls_workspace_bytes(n, p, opts) bytes,
+ *   256-byte aligned; it must outlive the handle.  Inputs may be freed once
+ *   gls_setup returns.
+ * Synchronizes `stream` before returning so that failures are reported:
+ *   GLS_ERR_NOT_SPD (*info = failing pivot, 1-based) or GLS_ERR_RANK
+ *   (*info = failing covariate, 1-based); *info = 0 on success.  `info` may be
+ *   NULL.  On failure *out is NULL. */
+gls_status gls_setup(gls_handle* out, int64_t n, int32_t p,
+                     const double* Phi, int64_t ld_phi, double h2,
+                     const double* XL, int64_t ld_xl, const double* y,
+                     void* workspace, size_t ws_bytes, const gls_opts* opts,
+                     void* stream, int64_t* info);
+
+/* One SNP block (Sec. 2.2 and the SNP loop of Sec. 2.1): X~_R,b = L^-1 X_R,b,
+ * the per-SNP products and the p x p solves.
+ * XR: n x mb (ld_xr >= n), 1 <= mb <= opts.block_cols; it is not modified.
+ * Outputs: b (p x mb, ld_b >= p), sigma2 (mb), v (mb), snp_status (mb).
+ * Asynchronous on `stream`.  Results depend only on each SNP's column, not on
+ * mb or on the column's position in the block (bitwise). */
+gls_status gls_block(gls_handle h, int32_t mb, const double* XR, int64_t ld_xr,
+                     double* b, int64_t ld_b, double* sigma2, double* v,
+                     int32_t* snp_status, void* stream);
+
+/* Per-stream timing and byte counts filled by gls_stream (may be NULL). */
+typedef struct {
+  int64_t blocks;        /* blocks processed                                  */
+  int64_t h2d_bytes;     /* host-to-device bytes                              */
+  int64_t d2h_bytes;     /* device-to-host bytes                              */
+  double wall_ms;        /* first copy enqueue to last result landed          */
+  double compute_ms;     /* sum over blocks of the block's device time        */
+} gls_stream_stats;
+
+/* Streamed study (Sec. 3.1, the GPU half of the double/triple buffering):
+ * SNP columns [col0, m) of XR_host (n x m, ld_xr >= n, page-locked host
+ * memory) are moved block by block into two device buffers (alpha computes
+ * while beta receives the next block on `copy_stream`), solved on
+ * `compute_stream`, and the results are copied into the host arrays
+ * b_host (p x m, ld = p), sigma2_host, v_host, status_host at the same
+ * column offsets.  Blocks of opts.block_cols columns; the last one is ragged.
+ * Returns after every result has landed.  col0 > 0 resumes an interrupted
+ * run: outputs for columns < col0 are not touched. */
+gls_status gls_stream(gls_handle h, int64_t m, int64_t col0,
+                      const double* XR_host, int64_t ld_xr,
+                      double* b_host, double* sigma2_host, double* v_host,
+                      int32_t* status_host, void* compute_stream, void* copy_stream,
+                      gls_stream_stats* stats_out);
+
+/* Adjoint of one SNP block (requires GLS_KEEP_FOR_GRAD at setup).
+ * Given cotangents b_bar (p x mb, ld p), sigma2_bar (mb), v_bar (mb) of the
+ * block's outputs, recomputes X~_R,b and accumulates into the handle the
+ * adjoints of L, y~, S_TL, r~_T and y~^T y~.  If XR_grad is not NULL it
+ * receives dL/dX_R,b (n x mb, ld_xr).  Asynchronous on `stream`. */
+gls_status gls_backward_block(gls_handle h, int32_t mb, const double* XR, int64_t ld_xr,
+                              const double* b_bar, const double* sigma2_bar,
+                              const double* v_bar, double* XR_grad, void* stream);
+
+/* Finishes the adjoint after all blocks: y_grad (n, may be NULL) and h2_grad
+ * (one double on the device, may be NULL), through y~ = L^-1 y, the Cholesky
+ * factorization and M = h2 Phi + (1 - h2) I.  Resets the accumulators.
+ * Asynchronous on `stream`. */
+gls_status gls_backward_finish(gls_handle h, double* y_grad, double* h2_grad, void* stream);
+
+/* Per-phase device time of the block path, measured with HIP events recorded
+ * around each phase's kernels on the caller's stream while profiling is on.
+ *   phase 0: triangular product X~_R,b = L^-1 X_R,b (plain, or the
+ *            low-precision bulk and corrections of the mixed forms)
+ *   phase 1: FP64 refinement residuals X_R,b - L X~_R,b (mixed forms)
+ *   phase 2: per-SNP products and p x p solves
+ *   phase 3: adjoint block work                                             */
+#define GLS_NUM_PHASES 4
+typedef struct {
+  int64_t launches[GLS_NUM_PHASES]; /* timed phase instances                 */
+  double ms[GLS_NUM_PHASES];        /* summed device milliseconds            */
+} gls_phase_stats;
+
+/* Turns event timing of the phases on (on != 0) or off.  Off by default. */
+gls_status gls_profile_enable(gls_handle h, int32_t on);
+
+/* Waits for the recorded events, adds their times into *out (zeroed first),
+ * and, if reset != 0, forgets them.  Host-synchronous on those events. */
+gls_status gls_profile_read(gls_handle h, gls_phase_stats* out, int32_t reset);
+
+/* Releases the handle (not the workspace).  NULL is allowed. */
+void gls_destroy(gls_handle h);
+
+const char* gls_status_string(gls_status s);
+const char* gls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLS_H */

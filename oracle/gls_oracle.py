@@ -87,7 +87,7 @@ def covariate_terms(L: np.ndarray, XL: np.ndarray, y: np.ndarray):
 
 def whiten_block(L: np.ndarray, XRb: np.ndarray) -> np.ndarray:
     """X~_R,b = L^-1 X_R,b for an n x mb block (Sec. 2.2: one trsm per block)."""
-    return scipy.linalg.solve_triangular(L, XRb, lower=True)
+    return scipy.linalg.solve_triangular(L, XRb, lower=True, check_finite=False)
 
 
 def snp_terms(XRt: np.ndarray, XLt: np.ndarray, yt: np.ndarray):

@@ -1,0 +1,492 @@
+// libgls: C-ABI entry points, workspace planning and the host-side drivers
+// of the streamed GWAS GLS solver (paper Sec. 2-3), for gfx950.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gemm_f64.hpp"
+#include "gls.h"
+#include "gls_internal.hpp"
+#include "setup_kernels.hpp"
+#include "snp_kernels.hpp"
+
+using namespace gls;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void set_err(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+}  // namespace
+
+namespace gls {
+
+gls_status hip_fail(hipError_t e, const char* what) {
+  set_err("%s: %s", what, hipGetErrorString(e));
+  return GLS_ERR_HIP;
+}
+
+gls_status arg_fail(const char* what) {
+  set_err("%s", what);
+  return GLS_ERR_ARG;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int64_t padded_n(int64_t n) { return (n + NPAD - 1) / NPAD * NPAD; }
+
+// Largest T1 buffer of the recursive factorization: (b - mid) * (mid - a) leaves.
+static int64_t recursion_temp_leaves(int a, int b) {
+  if (b - a <= 1) return 0;
+  int mid = (a + b) / 2;
+  int64_t here = (int64_t)(b - mid) * (mid - a);
+  return std::max(here, std::max(recursion_temp_leaves(a, mid), recursion_temp_leaves(mid, b)));
+}
+
+bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
+  if (n < 2 || p < 1 || p > PMAX || n <= p || !o || o->block_cols < 1) return false;
+  if (o->precision < GLS_FP64 || o->precision > GLS_BF16_IR) return false;
+  if (o->refine_sweeps < 0 || o->refine_sweeps > 4) return false;
+  if (n > (int64_t)1 << 20) return false;
+  const int64_t N = padded_n(n);
+  const int64_t bc = o->block_cols;
+  const int Kt = (int)(N / NB_LEAF);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  pl->n = n;
+  pl->p = p;
+  pl->N = N;
+  pl->bc = bc;
+  pl->off_info = take(256);
+  pl->off_small = take(sizeof(double) * 2048);
+  pl->off_gram = take(sizeof(double) * PMAX * PMAX);
+  pl->off_L = take(sizeof(double) * N * N);
+  pl->off_Linv = take(sizeof(double) * N * N);
+  pl->off_W = take(sizeof(double) * N * p);
+  int64_t tmp = std::max<int64_t>(N * bc, recursion_temp_leaves(0, Kt) * NB_LEAF * NB_LEAF);
+  tmp = std::max<int64_t>(tmp, N * p);
+  pl->off_Xt = take(sizeof(double) * tmp);
+  pl->off_buf0 = take(sizeof(double) * n * bc);
+  pl->off_buf1 = take(sizeof(double) * n * bc);
+  pl->off_ob = take(sizeof(double) * p * bc);
+  pl->off_os2 = take(sizeof(double) * bc);
+  pl->off_ov = take(sizeof(double) * bc);
+  pl->off_ost = take(sizeof(int32_t) * bc);
+  pl->total = off;
+  return true;
+}
+
+}  // namespace gls
+
+// ---------------------------------------------------------------------------
+// GEMM launch helpers
+
+namespace gls {
+
+template <bool TA, bool TB, int MAP>
+static void launch_gemm_cfg(GemmArgs g, hipStream_t s) {
+  constexpr int BM = 128, BN = 128, BK = 16;
+  const int Mt = (g.M + BM - 1) / BM;
+  g.M = Mt * BM;
+  const int Nt = (g.ncols + BN - 1) / BN;
+  if (Mt == 0 || Nt == 0) return;
+  if (MAP == MAP_XCD) {
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, 2, 2, TA, TB, MAP_XCD>), dim3(XcdMap::grid(Mt, Nt)), dim3(256), 0,
+                       s, g);
+  } else {
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, 2, 2, TA, TB, MAP_GRID>), dim3(Nt, Mt), dim3(256), 0, s, g);
+  }
+}
+
+void gemm(bool ta, bool tb, bool xcd_map, const GemmArgs& g, hipStream_t s) {
+  if (xcd_map) {
+    if (!ta && !tb) launch_gemm_cfg<false, false, MAP_XCD>(g, s);
+    else if (ta && !tb) launch_gemm_cfg<true, false, MAP_XCD>(g, s);
+    else if (!ta && tb) launch_gemm_cfg<false, true, MAP_XCD>(g, s);
+    else launch_gemm_cfg<true, true, MAP_XCD>(g, s);
+  } else {
+    if (!ta && !tb) launch_gemm_cfg<false, false, MAP_GRID>(g, s);
+    else if (ta && !tb) launch_gemm_cfg<true, false, MAP_GRID>(g, s);
+    else if (!ta && tb) launch_gemm_cfg<false, true, MAP_GRID>(g, s);
+    else launch_gemm_cfg<true, true, MAP_GRID>(g, s);
+  }
+}
+
+GemmArgs gemm_args(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int M,
+                   int ncols, int K, double alpha) {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.C = C;
+  g.ldc = ldc;
+  g.Cin = C;
+  g.ldcin = ldc;
+  g.M = M;
+  g.mvalid = M;
+  g.ncols = ncols;
+  g.K = K;
+  g.alpha = alpha;
+  g.beta = 0.0;
+  return g;
+}
+
+static int grid_for(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 65536);
+}
+
+// Recursive blocked Cholesky with the inverse factor built alongside.
+// Leaves [a, b) count NB_LEAF-row diagonal blocks of the N x N matrices.
+//   chol([A11 .; A21 A22]):  L11 = chol(A11), L11^-1 (leaf: in LDS)
+//                            L21 = A21 L11^-T,  A22 -= L21 L21^T
+//                            L22 = chol(A22),   L22^-1
+//                            (L^-1)21 = -L22^-1 L21 L11^-1
+static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
+  const int64_t N = c->N;
+  double* L = c->L;
+  double* Li = c->Linv;
+  if (b - a == 1) {
+    const int64_t r = (int64_t)a * NB_LEAF;
+    hipLaunchKernelGGL(leaf_potrf_trtri_kernel, dim3(1), dim3(256), 0, s, L + r + r * N, Li + r + r * N, N, (int)r,
+                       c->info);
+    return;
+  }
+  const int mid = (a + b) / 2;
+  chol_inv_rec(c, a, mid, s);
+  const int64_t r1 = (int64_t)a * NB_LEAF, r2 = (int64_t)mid * NB_LEAF;
+  const int w1 = (mid - a) * NB_LEAF, w2 = (b - mid) * NB_LEAF;
+  double* A21 = L + r2 + r1 * N;
+  double* A22 = L + r2 + r2 * N;
+  const double* Li11 = Li + r1 + r1 * N;
+  double* Li21 = Li + r2 + r1 * N;
+  const double* Li22 = Li + r2 + r2 * N;
+  double* T = c->Xt;  // w2 x w1, ld w2
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for((int64_t)w2 * w1)), dim3(256), 0, s, T, (int64_t)w2, A21, N, w2,
+                     w1);
+  {  // L21 = T * L11^-T   (op(B)[k][j] = Li11[j][k], non-zero for k <= j: upper)
+    GemmArgs g = gemm_args(T, w2, Li11, N, A21, N, w2, w1, w1, 1.0);
+    g.b_tri = TRI_UPPER;
+    g.b_diag = 0;
+    gemm(false, true, false, g, s);
+  }
+  {  // A22 -= L21 L21^T  (lower tiles)
+    GemmArgs g = gemm_args(A21, N, A21, N, A22, N, w2, w2, w1, -1.0);
+    g.beta = 1.0;
+    g.c_lower = 1;
+    g.c_diag = 0;
+    gemm(false, true, false, g, s);
+  }
+  chol_inv_rec(c, mid, b, s);
+  {  // T = L21 L11^-1   (op(B) = Li11 lower: non-zero for k >= j)
+    GemmArgs g = gemm_args(A21, N, Li11, N, T, w2, w2, w1, w1, 1.0);
+    g.b_tri = TRI_LOWER;
+    g.b_diag = 0;
+    gemm(false, false, false, g, s);
+  }
+  {  // (L^-1)21 = -L22^-1 T   (op(A) = Li22 lower: non-zero for k <= i)
+    GemmArgs g = gemm_args(Li22, N, T, w2, Li21, N, w2, w1, w2, -1.0);
+    g.a_tri = TRI_LOWER;
+    g.a_diag = 0;
+    gemm(false, false, false, g, s);
+  }
+}
+
+// X~ (N x mb, ld N) = L^-1 X   for an n x mb block X (ld ldx); rows >= n of X read as 0.
+void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, double* Xt, hipStream_t s) {
+  GemmArgs g = gemm_args(c->Linv, c->N, X, ldx, Xt, c->N, (int)c->N, mb, (int)c->n, 1.0);
+  g.a_tri = TRI_LOWER;
+  g.a_diag = 0;
+  g.map_desc = 1;
+  gemm(false, false, true, g, s);
+}
+
+template <int P>
+static void launch_snp_p(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,
+                         hipStream_t s) {
+  const int grid = (mb + SNP_PER_WG - 1) / SNP_PER_WG;
+  hipLaunchKernelGGL(snp_reduce_solve_kernel<P>, dim3(grid), dim3(64 * SNP_WAVES), 0, s, Xt, (int64_t)c->N, (int)c->N,
+                     mb, c->W, c->small, (int)c->n, b, ldb, s2, v, st);
+}
+
+void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,
+                      hipStream_t s) {
+  switch (c->p) {
+#define GLS_P_CASE(P) \
+  case P: launch_snp_p<P>(c, Xt, mb, b, ldb, s2, v, st, s); break;
+    GLS_P_CASE(1) GLS_P_CASE(2) GLS_P_CASE(3) GLS_P_CASE(4) GLS_P_CASE(5) GLS_P_CASE(6) GLS_P_CASE(7)
+    GLS_P_CASE(8) GLS_P_CASE(9) GLS_P_CASE(10) GLS_P_CASE(11) GLS_P_CASE(12) GLS_P_CASE(13) GLS_P_CASE(14)
+    GLS_P_CASE(15) GLS_P_CASE(16) GLS_P_CASE(17) GLS_P_CASE(18) GLS_P_CASE(19) GLS_P_CASE(20)
+#undef GLS_P_CASE
+    default: break;
+  }
+}
+
+}  // namespace gls
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+const char* gls_status_string(gls_status s) {
+  switch (s) {
+    case GLS_OK: return "ok";
+    case GLS_ERR_ARG: return "invalid argument";
+    case GLS_ERR_NOT_SPD: return "M is not positive definite";
+    case GLS_ERR_HIP: return "HIP runtime error";
+    case GLS_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case GLS_ERR_STATE: return "call not valid in this state";
+    case GLS_ERR_RANK: return "covariates are rank deficient";
+  }
+  return "unknown status";
+}
+
+const char* gls_last_error(void) { return g_err; }
+
+size_t gls_workspace_bytes(int64_t n, int32_t p, const gls_opts* opts) {
+  Plan pl;
+  if (!plan_workspace(n, p, opts, &pl)) return 0;
+  return pl.total;
+}
+
+gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, int64_t ld_phi, double h2,
+                     const double* XL, int64_t ld_xl, const double* y, void* workspace, size_t ws_bytes,
+                     const gls_opts* opts, void* stream, int64_t* info) {
+  if (info) *info = 0;
+  if (!out) return arg_fail("gls_setup: out is NULL");
+  *out = nullptr;
+  Plan pl;
+  if (!plan_workspace(n, p, opts, &pl)) return arg_fail("gls_setup: invalid n/p/opts (need 1 <= p <= 20, n > p)");
+  if (!Phi || ld_phi < n) return arg_fail("gls_setup: Phi is NULL or ld_phi < n");
+  if (p > 1 && (!XL || ld_xl < n)) return arg_fail("gls_setup: XL is NULL or ld_xl < n");
+  if (!y) return arg_fail("gls_setup: y is NULL");
+  if (!(h2 >= 0.0 && h2 <= 1.0)) return arg_fail("gls_setup: h2 must lie in [0, 1]");
+  if (!workspace || ((uintptr_t)workspace & 255)) {
+    set_err("gls_setup: workspace is NULL or not 256-byte aligned");
+    return GLS_ERR_WORKSPACE;
+  }
+  if (ws_bytes < pl.total) {
+    set_err("gls_setup: workspace has %zu bytes, needs %zu", ws_bytes, pl.total);
+    return GLS_ERR_WORKSPACE;
+  }
+  Ctx* c = new (std::nothrow) Ctx();
+  if (!c) return arg_fail("gls_setup: out of host memory");
+  c->plan = pl;
+  c->opts = *opts;
+  c->n = n;
+  c->p = p;
+  c->N = pl.N;
+  c->bc = pl.bc;
+  c->h2 = h2;
+  char* ws = static_cast<char*>(workspace);
+  c->info = reinterpret_cast<int*>(ws + pl.off_info);
+  c->small = reinterpret_cast<double*>(ws + pl.off_small);
+  c->gram = reinterpret_cast<double*>(ws + pl.off_gram);
+  c->L = reinterpret_cast<double*>(ws + pl.off_L);
+  c->Linv = reinterpret_cast<double*>(ws + pl.off_Linv);
+  c->W = reinterpret_cast<double*>(ws + pl.off_W);
+  c->Xt = reinterpret_cast<double*>(ws + pl.off_Xt);
+  c->buf[0] = reinterpret_cast<double*>(ws + pl.off_buf0);
+  c->buf[1] = reinterpret_cast<double*>(ws + pl.off_buf1);
+  c->ob = reinterpret_cast<double*>(ws + pl.off_ob);
+  c->os2 = reinterpret_cast<double*>(ws + pl.off_os2);
+  c->ov = reinterpret_cast<double*>(ws + pl.off_ov);
+  c->ost = reinterpret_cast<int*>(ws + pl.off_ost);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t N = c->N;
+
+  hipError_t e;
+  int hinfo[2] = {0, 0};
+  auto fail = [&](gls_status st) {
+    delete c;
+    return st;
+  };
+  // info[0]: failing pivot of M, info[1]: failing pivot of S_TL
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<double*>(c->info), (int64_t)4, 0.0);
+  hipLaunchKernelGGL(form_m_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->L, (int)N, (int)n, Phi, ld_phi, h2);
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Linv, N * N, 0.0);
+  chol_inv_rec(c, 0, (int)(N / NB_LEAF), s);
+  // [X~_L | y~] = L^-1 [X_L | y]
+  double* Wp = c->Xt;
+  hipLaunchKernelGGL(pack_covariates_kernel, dim3(grid_for(N * p)), dim3(256), 0, s, Wp, (int)N, (int)n, (int)p, XL,
+                     ld_xl, y);
+  {
+    GemmArgs g = gemm_args(c->Linv, N, Wp, N, c->W, N, (int)N, p, (int)N, 1.0);
+    g.a_tri = TRI_LOWER;
+    g.a_diag = 0;
+    gemm(false, false, false, g, s);
+  }
+  hipLaunchKernelGGL(gram_kernel, dim3(p * (p + 1) / 2), dim3(256), 0, s, c->W, (int)N, (int)p, c->gram);
+  hipLaunchKernelGGL(small_factor_kernel, dim3(1), dim3(64), 0, s, c->gram, (int)p, c->small, c->info + 1);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(hip_fail(e, "gls_setup: launch"));
+  if ((e = hipMemcpyAsync(hinfo, c->info, sizeof hinfo, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return fail(hip_fail(e, "gls_setup: info copy"));
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(hip_fail(e, "gls_setup: synchronize"));
+  if (hinfo[0] != 0) {
+    if (info) *info = hinfo[0];
+    set_err("gls_setup: M is not positive definite (leading minor %d)", hinfo[0]);
+    return fail(GLS_ERR_NOT_SPD);
+  }
+  if (hinfo[1] != 0) {
+    if (info) *info = hinfo[1];
+    set_err("gls_setup: S_TL = X~_L^T X~_L is not positive definite at covariate %d", hinfo[1]);
+    return fail(GLS_ERR_RANK);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if ((e = hipEventCreateWithFlags(&c->ev_copy[i], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_comp[i], hipEventDisableTiming)) != hipSuccess) {
+      gls_destroy(c);
+      return hip_fail(e, "gls_setup: event create");
+    }
+  }
+  c->ready = true;
+  *out = c;
+  return GLS_OK;
+}
+
+gls_status gls_block(gls_handle h, int32_t mb, const double* XR, int64_t ld_xr, double* b, int64_t ld_b,
+                     double* sigma2, double* v, int32_t* snp_status, void* stream) {
+  Ctx* c = h;
+  if (!c || !c->ready) {
+    set_err("gls_block: handle is not set up");
+    return GLS_ERR_STATE;
+  }
+  if (mb < 0 || mb > c->bc) return arg_fail("gls_block: mb must lie in [0, block_cols]");
+  if (mb == 0) return GLS_OK;
+  if (!XR || ld_xr < c->n) return arg_fail("gls_block: XR is NULL or ld_xr < n");
+  if (!b || ld_b < c->p || !sigma2 || !v || !snp_status) return arg_fail("gls_block: NULL output or ld_b < p");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gls_status st = block_forward(c, mb, XR, ld_xr, b, ld_b, sigma2, v, snp_status, s);
+  if (st != GLS_OK) return st;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "gls_block: launch");
+  return GLS_OK;
+}
+
+gls_status gls_profile_enable(gls_handle h, int32_t on) {
+  Ctx* c = h;
+  if (!c) return arg_fail("gls_profile_enable: NULL handle");
+  c->prof_on = on != 0;
+  return GLS_OK;
+}
+
+gls_status gls_profile_read(gls_handle h, gls_phase_stats* out, int32_t reset) {
+  Ctx* c = h;
+  if (!c || !out) return arg_fail("gls_profile_read: NULL argument");
+  for (const auto& r : c->prof_pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(e, "gls_profile_read");
+    c->prof_ms[r.phase] += ms;
+    c->prof_n[r.phase] += 1;
+    c->prof_free.push_back(r.a);
+    c->prof_free.push_back(r.b);
+  }
+  c->prof_pending.clear();
+  for (int i = 0; i < GLS_NUM_PHASES; ++i) {
+    out->launches[i] = c->prof_n[i];
+    out->ms[i] = c->prof_ms[i];
+    if (reset) {
+      c->prof_n[i] = 0;
+      c->prof_ms[i] = 0.0;
+    }
+  }
+  return GLS_OK;
+}
+
+void gls_destroy(gls_handle h) {
+  Ctx* c = h;
+  if (!c) return;
+  for (const auto& r : c->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2; ++i) {
+    if (c->ev_copy[i]) (void)hipEventDestroy(c->ev_copy[i]);
+    if (c->ev_comp[i]) (void)hipEventDestroy(c->ev_comp[i]);
+  }
+  delete c;
+}
+
+}  // extern "C"
+
+namespace gls {
+
+static hipEvent_t prof_event(Ctx* c) {
+  if (!c->prof_free.empty()) {
+    hipEvent_t e = c->prof_free.back();
+    c->prof_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+PhaseTimer::PhaseTimer(Ctx* c, int phase, hipStream_t s) : c_(c), phase_(phase), s_(s) {
+  if (!c_->prof_on) return;
+  a_ = prof_event(c_);
+  if (a_ && hipEventRecord(a_, s_) != hipSuccess) {
+    c_->prof_free.push_back(a_);
+    a_ = nullptr;
+  }
+}
+
+PhaseTimer::~PhaseTimer() {
+  if (!a_) return;
+  hipEvent_t b = prof_event(c_);
+  if (b && hipEventRecord(b, s_) == hipSuccess) {
+    c_->prof_pending.push_back({phase_, a_, b});
+  } else {
+    c_->prof_free.push_back(a_);
+    if (b) c_->prof_free.push_back(b);
+  }
+}
+
+gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double* b, int64_t ld_b, double* s2,
+                         double* v, int* st, hipStream_t s) {
+  {
+    PhaseTimer t(c, PH_WHITEN, s);
+    whiten_fp64(c, XR, ld_xr, mb, c->Xt, s);
+  }
+  {
+    PhaseTimer t(c, PH_SNP, s);
+    snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
+  }
+  return GLS_OK;
+}
+
+}  // namespace gls
+
+extern "C" gls_status gls_backward_block(gls_handle h, int32_t, const double*, int64_t, const double*, const double*,
+                                         const double*, double*, void*) {
+  (void)h;
+  set_err("gls_backward_block: the adjoint is not available in this build");
+  return GLS_ERR_STATE;
+}
+
+extern "C" gls_status gls_backward_finish(gls_handle h, double*, double*, void*) {
+  (void)h;
+  set_err("gls_backward_finish: the adjoint is not available in this build");
+  return GLS_ERR_STATE;
+}

@@ -1,0 +1,93 @@
+// Internal state of a libgls handle and the shared host-side helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "gls.h"
+
+namespace gls {
+
+constexpr int PMAX = 20;    // p ranges from 4 to 20 in practice (Sec. 1.4)
+constexpr int64_t NPAD = 256;  // internal row padding of every n-sized dimension
+
+// Byte offsets of every region inside the caller's workspace.
+struct Plan {
+  int64_t n = 0, N = 0, bc = 0;
+  int p = 0;
+  size_t off_info = 0, off_small = 0, off_gram = 0;
+  size_t off_L = 0, off_Linv = 0, off_W = 0, off_Xt = 0;
+  size_t off_buf0 = 0, off_buf1 = 0;
+  size_t off_ob = 0, off_os2 = 0, off_ov = 0, off_ost = 0;
+  size_t total = 0;
+};
+
+}  // namespace gls
+
+struct gls_ctx {
+  gls::Plan plan;
+  gls_opts opts{};
+  int64_t n = 0, N = 0, bc = 0;
+  int p = 0;
+  double h2 = 0.0;
+  bool ready = false;
+  // device regions (inside the workspace)
+  int* info = nullptr;      // [0] pivot of M, [1] pivot of S_TL
+  double* small = nullptr;  // factor of S_TL and hoisted right-hand side
+  double* gram = nullptr;   // [X~_L | y~]^T [X~_L | y~]  (p x p)
+  double* L = nullptr;      // N x N lower Cholesky factor of M (identity padding)
+  double* Linv = nullptr;   // N x N lower, L^-1
+  double* W = nullptr;      // N x p, [X~_L | y~]
+  double* Xt = nullptr;     // N x block_cols, X~_R of the current block (also setup scratch)
+  double* buf[2] = {nullptr, nullptr};  // streaming: alpha / beta SNP blocks, n x block_cols
+  double* ob = nullptr;     // streaming outputs: b (p x block_cols)
+  double* os2 = nullptr;
+  double* ov = nullptr;
+  int* ost = nullptr;
+  hipEvent_t ev_copy[2] = {nullptr, nullptr};
+  hipEvent_t ev_comp[2] = {nullptr, nullptr};
+  // phase timing (gls_profile_*)
+  struct ProfRec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_free;
+  int64_t prof_n[GLS_NUM_PHASES] = {0, 0, 0, 0};
+  double prof_ms[GLS_NUM_PHASES] = {0, 0, 0, 0};
+};
+
+namespace gls {
+
+using Ctx = gls_ctx;
+
+enum { PH_WHITEN = 0, PH_RESIDUAL = 1, PH_SNP = 2, PH_BACKWARD = 3 };
+
+// Records an event pair around a phase on stream s when profiling is on.
+class PhaseTimer {
+ public:
+  PhaseTimer(Ctx* c, int phase, hipStream_t s);
+  ~PhaseTimer();
+
+ private:
+  Ctx* c_;
+  int phase_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr;
+};
+
+gls_status hip_fail(hipError_t e, const char* what);
+gls_status arg_fail(const char* what);
+int64_t padded_n(int64_t n);
+bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl);
+
+void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, double* Xt, hipStream_t s);
+void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,
+                      hipStream_t s);
+gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double* b, int64_t ld_b, double* s2,
+                         double* v, int* st, hipStream_t s);
+
+}  // namespace gls

@@ -1,0 +1,199 @@
+// Setup-phase kernels: forming M, the in-LDS factorization and inversion of
+// the diagonal blocks, packing, and the small Gram matrix of [X~_L | y~].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gls {
+
+// Leaf (diagonal block) size of the blocked Cholesky / inversion.
+constexpr int NB_LEAF = 64;
+
+// L <- M = h2 * Phi + (1 - h2) * I in the lower triangle of the leading n x n
+// block (read from Phi's lower triangle), identity on the padding rows
+// n..N-1, zeros above the diagonal.  N x N column-major, ld = N.
+__global__ void form_m_kernel(double* __restrict__ L, int N, int n,
+                              const double* __restrict__ Phi, int64_t ld_phi, double h2) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)N * N;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx % N);
+    int j = (int)(idx / N);
+    double v = 0.0;
+    if (i >= j) {
+      if (i < n) v = h2 * Phi[(int64_t)i + (int64_t)j * ld_phi] + (i == j ? (1.0 - h2) : 0.0);
+      else if (i == j) v = 1.0;
+    }
+    L[idx] = v;
+  }
+}
+
+__global__ void fill_kernel(double* __restrict__ p, int64_t count, double v) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; idx < count; idx += (int64_t)gridDim.x * blockDim.x) p[idx] = v;
+}
+
+// dst (rows x cols, ld_dst) <- src (rows x cols, ld_src)
+__global__ void copy2d_kernel(double* __restrict__ dst, int64_t ld_dst,
+                              const double* __restrict__ src, int64_t ld_src, int rows, int cols) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)rows * cols;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx % rows);
+    int j = (int)(idx / rows);
+    dst[(int64_t)i + (int64_t)j * ld_dst] = src[(int64_t)i + (int64_t)j * ld_src];
+  }
+}
+
+// Wpack (N x p, ld N) <- [X_L | y] with zero rows n..N-1.
+__global__ void pack_covariates_kernel(double* __restrict__ Wp, int N, int n, int p,
+                                       const double* __restrict__ XL, int64_t ld_xl,
+                                       const double* __restrict__ y) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)N * p;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx % N);
+    int j = (int)(idx / N);
+    double v = 0.0;
+    if (i < n) v = (j < p - 1) ? XL[(int64_t)i + (int64_t)j * ld_xl] : y[i];
+    Wp[idx] = v;
+  }
+}
+
+// One diagonal block of the blocked factorization, entirely in LDS:
+//   Cholesky (right-looking, one column per step) of the NB_LEAF x NB_LEAF
+//   lower block at A (ld), then its inverse by column-wise forward
+//   substitution.  Writes the factor (zero upper part) back to A and the
+//   inverse (zero upper part) to Ainv (ld).  A non-positive or NaN pivot
+//   sets *info = row0 + j + 1 if *info is still 0 (the 1-based global pivot;
+//   blocks are processed in order so the first failure wins).
+__global__ __launch_bounds__(256) void leaf_potrf_trtri_kernel(double* __restrict__ A, double* __restrict__ Ainv,
+                                                               int64_t ld, int row0, int* __restrict__ info) {
+  constexpr int B = NB_LEAF;
+  constexpr int S = B + 1;
+  __shared__ double a[B * S];   // a[i + j * S] = A[i][j]
+  __shared__ double x[B * S];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < B * B; idx += blockDim.x) {
+    int i = idx % B, j = idx / B;
+    a[i + j * S] = (i >= j) ? A[(int64_t)i + (int64_t)j * ld] : 0.0;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < B; ++j) {
+    if (tid == 0) {
+      double d = a[j + j * S];
+      if (!(d > 0.0)) {
+        if (!bad) {
+          bad = 1;
+          if (*info == 0) *info = row0 + j + 1;
+        }
+      }
+      a[j + j * S] = sqrt(d);
+    }
+    __syncthreads();
+    const double djj = a[j + j * S];
+    for (int i = j + 1 + tid; i < B; i += blockDim.x) a[i + j * S] /= djj;
+    __syncthreads();
+    const int w = B - j - 1;
+    for (int idx = tid; idx < w * w; idx += blockDim.x) {
+      int ii = j + 1 + idx % w;
+      int kk = j + 1 + idx / w;
+      if (ii >= kk) a[ii + kk * S] -= a[ii + j * S] * a[kk + j * S];
+    }
+    __syncthreads();
+  }
+  // inverse: column jj of X solves L x = e_jj (one thread per column)
+  if (tid < B) {
+    const int jj = tid;
+    for (int i = 0; i < B; ++i) {
+      double v = 0.0;
+      if (i >= jj) {
+        double s = (i == jj) ? 1.0 : 0.0;
+        for (int k = jj; k < i; ++k) s -= a[i + k * S] * x[k + jj * S];
+        v = s / a[i + i * S];
+      }
+      x[i + jj * S] = v;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < B * B; idx += blockDim.x) {
+    int i = idx % B, j = idx / B;
+    A[(int64_t)i + (int64_t)j * ld] = (i >= j) ? a[i + j * S] : 0.0;
+    Ainv[(int64_t)i + (int64_t)j * ld] = (i >= j) ? x[i + j * S] : 0.0;
+  }
+}
+
+// G[j][k] = sum_r W[r][j] * W[r][k] for j >= k (p x p, both triangles written);
+// one workgroup per (j, k) pair, fixed-order tree reduction.
+__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ W, int N, int p, double* __restrict__ G) {
+  __shared__ double red[256];
+  int pair = blockIdx.x;
+  int j = 0;
+  while ((j + 1) * (j + 2) / 2 <= pair) ++j;
+  int k = pair - j * (j + 1) / 2;
+  double s = 0.0;
+  const double* wj = W + (int64_t)j * N;
+  const double* wk = W + (int64_t)k * N;
+  for (int r = threadIdx.x; r < N; r += 256) s += wj[r] * wk[r];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    G[j + k * p] = red[0];
+    G[k + j * p] = red[0];
+  }
+}
+
+// Layout of the small per-study constants used by the per-SNP solve.
+//   Lt  : q x q lower Cholesky factor of S_TL (q = p - 1), column-major
+//   zT  : q      Lt^-1 r~_T
+//   c   : 1      y~^T y~
+//   qres: 1      c - zT^T zT   (residual of y~ on X~_L)
+struct SmallLayout {
+  static __host__ __device__ int Lt(int) { return 0; }
+  static __host__ __device__ int zT(int p) { return (p - 1) * (p - 1); }
+  static __host__ __device__ int c(int p) { return (p - 1) * (p - 1) + (p - 1); }
+  static __host__ __device__ int qres(int p) { return c(p) + 1; }
+  static __host__ __device__ int size(int p) { return qres(p) + 1; }
+};
+
+// Single-thread factorization of S_TL = G[0:q, 0:q] and the hoisted
+// right-hand side.  Sets *info_rank = j + 1 for the first non-positive pivot.
+__global__ void small_factor_kernel(const double* __restrict__ G, int p, double* __restrict__ small,
+                                    int* __restrict__ info_rank) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int q = p - 1;
+  double* Lt = small + SmallLayout::Lt(p);
+  double* zT = small + SmallLayout::zT(p);
+  for (int j = 0; j < q; ++j) {
+    double d = G[j + j * p];
+    for (int k = 0; k < j; ++k) d -= Lt[j + k * q] * Lt[j + k * q];
+    if (!(d > 0.0) && *info_rank == 0) *info_rank = j + 1;
+    d = sqrt(d);
+    Lt[j + j * q] = d;
+    for (int i = j + 1; i < q; ++i) {
+      double s = G[i + j * p];
+      for (int k = 0; k < j; ++k) s -= Lt[i + k * q] * Lt[j + k * q];
+      Lt[i + j * q] = s / d;
+    }
+    for (int i = 0; i < j; ++i) Lt[i + j * q] = 0.0;
+  }
+  double zz = 0.0;
+  for (int j = 0; j < q; ++j) {
+    double s = G[j + q * p];
+    for (int k = 0; k < j; ++k) s -= Lt[j + k * q] * zT[k];
+    zT[j] = s / Lt[j + j * q];
+    zz += zT[j] * zT[j];
+  }
+  const double c = G[q + q * p];
+  small[SmallLayout::c(p)] = c;
+  small[SmallLayout::qres(p)] = c - zz;
+}
+
+}  // namespace gls

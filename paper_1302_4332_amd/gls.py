@@ -1,0 +1,227 @@
+"""Python binding of libgls (ctypes).  Argument marshalling only: every step
+of the solve runs in the HIP library.  PyTorch provides device memory,
+pinned host memory and streams.
+
+Layouts (torch row-major views of the library's column-major matrices):
+  Phi  (n, n)       symmetric
+  XL   (n, p-1)     passed to the library as (p-1, n) contiguous
+  y    (n,)
+  XR   (mb, n)      one SNP per row  == column-major n x mb
+  b    (mb, p)      one SNP per row  == column-major p x mb
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgls.so")
+
+GLS_FP64, GLS_FP32_IR, GLS_FP16_IR, GLS_BF16_IR = 0, 1, 2, 3
+PRECISIONS = {"fp64": GLS_FP64, "fp32_ir": GLS_FP32_IR, "fp16_ir": GLS_FP16_IR, "bf16_ir": GLS_BF16_IR}
+GLS_KEEP_FOR_GRAD = 1
+
+STATUS = {0: "GLS_OK", -1: "GLS_ERR_ARG", -2: "GLS_ERR_NOT_SPD", -3: "GLS_ERR_HIP",
+          -4: "GLS_ERR_WORKSPACE", -5: "GLS_ERR_STATE", -6: "GLS_ERR_RANK"}
+
+
+class GlsOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("refine_sweeps", ctypes.c_int32),
+                ("block_cols", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class GlsStreamStats(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int64), ("h2d_bytes", ctypes.c_int64), ("d2h_bytes", ctypes.c_int64),
+                ("wall_ms", ctypes.c_double), ("compute_ms", ctypes.c_double)]
+
+
+class GlsPhaseStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4)]
+
+
+PHASES = ("whiten", "residual", "snp", "backward")
+
+
+class GLSError(RuntimeError):
+    def __init__(self, status: int, msg: str, info: int = 0):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.info = info
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+
+# name -> (restype, argtypes); every symbol include/gls.h declares
+SIGNATURES = {
+    "gls_workspace_bytes": (ctypes.c_size_t, [_I64, _I32, ctypes.POINTER(GlsOpts)]),
+    "gls_setup": (ctypes.c_int, [ctypes.POINTER(_P), _I64, _I32, _P, _I64, _D, _P, _I64, _P, _P,
+                                 ctypes.c_size_t, ctypes.POINTER(GlsOpts), _P, ctypes.POINTER(_I64)]),
+    "gls_block": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _P, _P, _P]),
+    "gls_stream": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
+                                  ctypes.POINTER(GlsStreamStats)]),
+    "gls_backward_block": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
+    "gls_backward_finish": (ctypes.c_int, [_P, _P, _P, _P]),
+    "gls_profile_enable": (ctypes.c_int, [_P, _I32]),
+    "gls_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(GlsPhaseStats), _I32]),
+    "gls_destroy": (None, [_P]),
+    "gls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "gls_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1302_4332_amd.build_lib`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, info: int = 0):
+    if status != 0:
+        raise GLSError(status, lib().gls_last_error().decode(), info)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(s=None):
+    s = torch.cuda.current_stream() if s is None else s
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype=torch.float64, cuda=True):
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if cuda and not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_opts(block_cols: int, precision="fp64", refine_sweeps: int = 0, keep_for_grad: bool = False) -> GlsOpts:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return GlsOpts(prec, int(refine_sweeps), int(block_cols), GLS_KEEP_FOR_GRAD if keep_for_grad else 0)
+
+
+def workspace_bytes(n: int, p: int, opts: GlsOpts) -> int:
+    return int(lib().gls_workspace_bytes(n, p, ctypes.byref(opts)))
+
+
+class GLSContext:
+    """One study: setup on construction, then SNP blocks.
+
+    Phi (n, n), XL (n, p-1), y (n,) are float64 CUDA tensors.
+    """
+
+    def __init__(self, Phi, h2, XL, y, *, block_cols: int, precision="fp64", refine_sweeps: int = 0,
+                 keep_for_grad: bool = False, stream=None):
+        _need(Phi, "Phi")
+        _need(y, "y")
+        n = Phi.shape[0]
+        if XL is None:
+            XL = torch.empty((n, 0), dtype=torch.float64, device=Phi.device)
+        p = XL.shape[1] + 1
+        XLc = XL.t().contiguous() if XL.shape[1] else None
+        self.n, self.p = n, p
+        self.opts = make_opts(block_cols, precision, refine_sweeps, keep_for_grad)
+        nbytes = workspace_bytes(n, p, self.opts)
+        if nbytes == 0:
+            raise GLSError(-1, f"invalid sizes or options (n={n}, p={p}, block_cols={block_cols})")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=Phi.device)
+        h = ctypes.c_void_p()
+        info = ctypes.c_int64(0)
+        st = lib().gls_setup(ctypes.byref(h), n, p, _ptr(Phi), n, float(h2), _ptr(XLc), n, _ptr(y),
+                             _ptr(self.workspace), nbytes, ctypes.byref(self.opts), _stream(stream),
+                             ctypes.byref(info))
+        _check(st, info.value)
+        self.handle = h
+        self.block_cols = block_cols
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gls_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, on: bool = True):
+        _check(lib().gls_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{phase: (timed launches, summed device ms)} from the library's HIP events."""
+        ps = GlsPhaseStats()
+        _check(lib().gls_profile_read(self.handle, ctypes.byref(ps), 1 if reset else 0))
+        return {name: (int(ps.launches[i]), float(ps.ms[i])) for i, name in enumerate(PHASES)}
+
+    def block_into(self, XR, b, sigma2, v, status, stream=None):
+        """Solve one block into caller-provided outputs (no allocation)."""
+        _need(XR, "XR")
+        mb = XR.shape[0]
+        if XR.dim() != 2 or XR.shape[1] != self.n:
+            raise ValueError(f"XR must have shape (mb, {self.n})")
+        for t, name, dt in ((b, "b", torch.float64), (sigma2, "sigma2", torch.float64),
+                            (v, "v", torch.float64), (status, "status", torch.int32)):
+            _need(t, name, dt)
+            if t.shape[0] != mb or (name == "b" and tuple(t.shape) != (mb, self.p)):
+                raise ValueError(f"{name} has the wrong shape {tuple(t.shape)}")
+        st = lib().gls_block(self.handle, mb, _ptr(XR), self.n,
+                             _ptr(b), self.p, _ptr(sigma2), _ptr(v), _ptr(status), _stream(stream))
+        _check(st)
+
+    def block(self, XR, stream=None):
+        """XR: (mb, n) float64 CUDA.  Returns b (mb, p), sigma2, v, status."""
+        mb = XR.shape[0]
+        dev = XR.device
+        b = torch.empty((mb, self.p), dtype=torch.float64, device=dev)
+        s2 = torch.empty(mb, dtype=torch.float64, device=dev)
+        v = torch.empty(mb, dtype=torch.float64, device=dev)
+        status = torch.empty(mb, dtype=torch.int32, device=dev)
+        self.block_into(XR, b, s2, v, status, stream)
+        return b, s2, v, status
+
+    def stream(self, XR_host, col0: int = 0, out=None, compute_stream=None, copy_stream=None):
+        """Stream SNPs [col0, m) of a pinned host tensor XR_host (m, n).
+
+        Returns (b, sigma2, v, status) host tensors and the stats struct.
+        """
+        _need(XR_host, "XR_host", cuda=False)
+        m = XR_host.shape[0]
+        if out is None:
+            out = (torch.full((m, self.p), float("nan"), dtype=torch.float64).pin_memory(),
+                   torch.full((m,), float("nan"), dtype=torch.float64).pin_memory(),
+                   torch.full((m,), float("nan"), dtype=torch.float64).pin_memory(),
+                   torch.full((m,), -1, dtype=torch.int32).pin_memory())
+        b, s2, v, status = out
+        for t, name, dt, shape in ((b, "b", torch.float64, (m, self.p)), (s2, "sigma2", torch.float64, (m,)),
+                                   (v, "v", torch.float64, (m,)), (status, "status", torch.int32, (m,))):
+            _need(t, name, dt, cuda=False)
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+        stats = GlsStreamStats()
+        cs = compute_stream or torch.cuda.current_stream()
+        xs = copy_stream or torch.cuda.Stream()
+        st = lib().gls_stream(self.handle, m, col0, _ptr(XR_host), self.n, _ptr(b), _ptr(s2), _ptr(v),
+                              _ptr(status), ctypes.c_void_p(cs.cuda_stream), ctypes.c_void_p(xs.cuda_stream),
+                              ctypes.byref(stats))
+        _check(st)
+        return (b, s2, v, status), stats
