@@ -141,7 +141,7 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None, "traffic": None,
-                "kernel": "gemm_f64_kernel (X~ = L^-1 X, XCD map)",
+                "kernel": "gemm_f64_kernel<64,64,16,1,4,false,false,MAP_XCD,VEC,M4> (X~ = L^-1 X)",
                 "launch_ms_avg": wms / wl if wl else None, "launches": wl,
                 "flops_per_snp": float(n) * n}
     out = {

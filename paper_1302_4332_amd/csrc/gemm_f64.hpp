@@ -12,12 +12,22 @@
 //
 // Tiles are BM x BN per workgroup, staged through LDS in BK-deep slices with
 // a register prefetch of the next slice and double-buffered LDS.  Each wave
-// owns a (BM/WAVES_M) x (BN/WAVES_N) sub-tile built from 16x16 accumulators
-// of v_mfma_f64_16x16x4f64.  Operand layout of that instruction (64 lanes):
+// owns a (BM/WAVES_M) x (BN/WAVES_N) sub-tile.  Two FP64 matrix instructions
+// are supported (operand layouts checked on gfx950 with one-hot operands):
+//
+//  v_mfma_f64_16x16x4f64 (M4 = false), 16x16 accumulators:
 //   A fragment: lane l holds A[l % 16][l / 16]  (16 rows x 4 k)
 //   B fragment: lane l holds B[l / 16][l % 16]  (4 k x 16 columns)
 //   accumulator: lane l, element t holds C[l / 16 + 4 * t][l % 16]
-//   (rows interleaved by 4; checked on gfx950 with one-hot operands).
+//
+//  v_mfma_f64_4x4x4_4b_f64 (M4 = true): four independent 4x4x4 products,
+//   block b = (l >> 2) & 3 of lane l; A[b][l & 3][l >> 4], B[b][l >> 4][l & 3],
+//   D[b][l >> 4][l & 3].  Taking the four blocks as four consecutive 4-row
+//   blocks of a 16-row strip makes the A fragment identical to the one above
+//   (A[l % 16][l / 16]); the B fragment is a 4-column slice B[l / 16][l % 4]
+//   shared by the four blocks, and the lane's one accumulator holds
+//   C[4 * ((l >> 2) & 3) + (l >> 4)][l & 3].  On gfx950 this form sustains
+//   close to the FP64 peak, about 1.6x the 16x16x4 form.
 //
 // Every output element is summed over the same k order whatever the block
 // width or the tile's column position, so results are bitwise independent
@@ -47,30 +57,36 @@ struct GemmArgs {
   int a_tri, a_diag;   // LOWER: op(A)[i,k] = 0 for k > i + a_diag; UPPER: for k < i + a_diag
   int b_tri, b_diag;   // LOWER: op(B)[k,j] = 0 for k < j + b_diag; UPPER: for k > j + b_diag
   int c_lower, c_diag; // skip tiles whose every (i, j) has i < j + c_diag
-  // MAP_XCD only: row tiles handled heavy-first (desc = rows with most k first)
+  // MAP_XCD only: row tiles handled heavy-first (desc = rows with most k first);
+  // map_gm x map_gn tiles per co-resident group on one XCD (0 = defaults)
   int map_desc;
+  int map_gm, map_gn;
 };
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
-// Row/column tile counts and workgroup count of the XCD-aware mapping.
-// Row tiles are dealt to the 8 XCDs in a snake order (balanced k-work);
-// on each XCD a group of GM local row tiles x GN column tiles runs together
-// so both operand strips are shared through that XCD's L2.
+// XCD-aware workgroup -> tile mapping.  Workgroups are dispatched to the 8
+// XCDs round-robin (workgroup id % 8), so row tiles are dealt to the XCDs in
+// a snake order (balanced k-work) and, on each XCD, groups of GM local row
+// tiles x GN column tiles run together so the operand strips they share stay
+// in that XCD's L2.  Row groups are issued heavy-first.
 struct XcdMap {
-  static constexpr int GM = 4;
-  static constexpr int GN = 16;
+  static constexpr int GM_DEFAULT = 1;   // measured best on gfx950 for the
+  static constexpr int GN_DEFAULT = 16;  // n = 10,000 per-block product
+  __host__ __device__ static int gm(const GemmArgs& g) { return g.map_gm > 0 ? g.map_gm : GM_DEFAULT; }
+  __host__ __device__ static int gn(const GemmArgs& g) { return g.map_gn > 0 ? g.map_gn : GN_DEFAULT; }
   __host__ __device__ static int rounds(int Mt) { return (Mt + 7) / 8; }
-  __host__ __device__ static int slots_per_xcd(int Mt, int Nt) {
+  __host__ __device__ static int slots_per_xcd(int Mt, int Nt, int GM, int GN) {
     int R = rounds(Mt);
     int rg = (R + GM - 1) / GM;
     int cg = (Nt + GN - 1) / GN;
     return rg * cg * GM * GN;
   }
-  __host__ static int grid(int Mt, int Nt) { return 8 * slots_per_xcd(Mt, Nt); }
+  __host__ static int grid(const GemmArgs& g, int Mt, int Nt) { return 8 * slots_per_xcd(Mt, Nt, gm(g), gn(g)); }
   // returns false for an idle slot
-  __device__ static bool tile(int bid, int Mt, int Nt, int desc, int* ti, int* tj) {
+  __device__ static bool tile(const GemmArgs& ga, int bid, int Mt, int Nt, int* ti, int* tj) {
+    const int GM = gm(ga), GN = gn(ga);
     int x = bid & 7;
     int s = bid >> 3;
     int R = rounds(Mt);
@@ -86,13 +102,118 @@ struct XcdMap {
     int pos = (kl & 1) ? (7 - x) : x;
     int ro = kl * 8 + pos;
     if (ro >= Mt) return false;
-    *ti = desc ? (Mt - 1 - ro) : ro;
+    *ti = ga.map_desc ? (Mt - 1 - ro) : ro;
     *tj = j;
     return true;
   }
 };
 
-template <int BM, int BN, int BK, int WAVES_M, int WAVES_N, bool TRANS_A, bool TRANS_B, int MAP>
+template <int BM, int BN, int BK, int NT, bool TRANS_A, bool TRANS_B, bool VEC>
+struct Stager {
+  static constexpr int SA = BM + 16;   // row strides (doubles): +16 puts k and k+1 on
+  static constexpr int SB = BN + 16;   // opposite halves of the LDS banks
+  static constexpr int W = VEC ? 8 : 1;
+  static constexpr int TA = BM * BK / W;   // chunks (or doubles) per slice
+  static constexpr int TB = BN * BK / W;
+  static constexpr int CA = (TA + NT - 1) / NT;   // per thread (the last round may be partial)
+  static constexpr int CB = (TB + NT - 1) / NT;
+  static_assert(TA % NT == 0 || NT % TA == 0, "loader split");
+  static_assert(TB % NT == 0 || NT % TB == 0, "loader split");
+  double ra[CA * W], rb[CB * W];
+
+  __device__ __forceinline__ static void vload8(double* dst, const double* src) {
+    const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2 v = s2[q];
+      dst[2 * q] = v.x;
+      dst[2 * q + 1] = v.y;
+    }
+  }
+
+  __device__ __forceinline__ void load(const GemmArgs& g, int i0, int j0, int kt, int tid) {
+#pragma unroll
+    for (int e = 0; e < CA; ++e) {
+      const int c = tid + e * NT;
+      if (TA < NT && c >= TA) break;
+      int i, k;
+      if (!TRANS_A) { i = (c % (BM / W)) * W; k = c / (BM / W); }
+      else          { k = (c % (BK / W)) * W; i = c / (BK / W); }
+      const int gi = i0 + i, gk = kt + k;
+      if (VEC) {
+        if (gi < g.mvalid && gk < g.K) {
+          vload8(&ra[e * 8], TRANS_A ? g.A + (int64_t)gk + (int64_t)gi * g.lda : g.A + (int64_t)gi + (int64_t)gk * g.lda);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) ra[e * 8 + q] = 0.0;
+        }
+      } else {
+        ra[e] = (gi < g.mvalid && gk < g.K)
+                    ? (TRANS_A ? g.A[(int64_t)gk + (int64_t)gi * g.lda] : g.A[(int64_t)gi + (int64_t)gk * g.lda])
+                    : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+      const int c = tid + e * NT;
+      if (TB < NT && c >= TB) break;
+      int j, k;
+      if (!TRANS_B) { k = (c % (BK / W)) * W; j = c / (BK / W); }
+      else          { j = (c % (BN / W)) * W; k = c / (BN / W); }
+      const int gj = j0 + j, gk = kt + k;
+      if (VEC) {
+        if (gj < g.ncols && gk < g.K) {
+          vload8(&rb[e * 8], TRANS_B ? g.B + (int64_t)gj + (int64_t)gk * g.ldb : g.B + (int64_t)gk + (int64_t)gj * g.ldb);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) rb[e * 8 + q] = 0.0;
+        }
+      } else {
+        rb[e] = (gj < g.ncols && gk < g.K)
+                    ? (TRANS_B ? g.B[(int64_t)gj + (int64_t)gk * g.ldb] : g.B[(int64_t)gk + (int64_t)gj * g.ldb])
+                    : 0.0;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(double* As, double* Bs, int tid) const {
+#pragma unroll
+    for (int e = 0; e < CA; ++e) {
+      const int c = tid + e * NT;
+      if (TA < NT && c >= TA) break;
+      int i, k;
+      if (!TRANS_A) { i = (c % (BM / W)) * W; k = c / (BM / W); }
+      else          { k = (c % (BK / W)) * W; i = c / (BK / W); }
+      if (VEC && !TRANS_A) {
+        double2* d = reinterpret_cast<double2*>(As + k * SA + i);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = double2{ra[e * 8 + 2 * q], ra[e * 8 + 2 * q + 1]};
+      } else {
+#pragma unroll
+        for (int q = 0; q < W; ++q) As[(k + (TRANS_A ? q : 0)) * SA + i + (TRANS_A ? 0 : q)] = ra[e * W + q];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+      const int c = tid + e * NT;
+      if (TB < NT && c >= TB) break;
+      int j, k;
+      if (!TRANS_B) { k = (c % (BK / W)) * W; j = c / (BK / W); }
+      else          { j = (c % (BN / W)) * W; k = c / (BN / W); }
+      if (VEC && TRANS_B) {
+        double2* d = reinterpret_cast<double2*>(Bs + k * SB + j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = double2{rb[e * 8 + 2 * q], rb[e * 8 + 2 * q + 1]};
+      } else {
+#pragma unroll
+        for (int q = 0; q < W; ++q) Bs[(k + (TRANS_B ? 0 : q)) * SB + j + (TRANS_B ? q : 0)] = rb[e * W + q];
+      }
+    }
+  }
+};
+
+template <int BM, int BN, int BK, int WAVES_M, int WAVES_N, bool TRANS_A, bool TRANS_B, int MAP, bool VEC,
+          bool M4 = true>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
 void gemm_f64_kernel(GemmArgs g) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
@@ -100,13 +221,11 @@ void gemm_f64_kernel(GemmArgs g) {
   constexpr int WTN = BN / WAVES_N;
   constexpr int FM = WTM / 16;
   constexpr int FN = WTN / 16;
-  constexpr int EA = BM * BK / NT;
-  constexpr int EB = BN * BK / NT;
-  constexpr int SA = BM + 2;   // LDS row strides (doubles); +2 staggers banks
-  constexpr int SB = BN + 2;
+  using St = Stager<BM, BN, BK, NT, TRANS_A, TRANS_B, VEC>;
+  constexpr int SA = St::SA;
+  constexpr int SB = St::SB;
   static_assert(BM % (16 * WAVES_M) == 0 && BN % (16 * WAVES_N) == 0, "tile");
-  static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "loader");
-  static_assert(BK % 4 == 0, "k step");
+  static_assert(BK % 8 == 0, "k step");
 
   __shared__ double As[2][BK * SA];
   __shared__ double Bs[2][BK * SB];
@@ -115,7 +234,7 @@ void gemm_f64_kernel(GemmArgs g) {
   if (MAP == MAP_XCD) {
     const int Mt = g.M / BM;
     const int Nt = (g.ncols + BN - 1) / BN;
-    if (!XcdMap::tile(blockIdx.x, Mt, Nt, g.map_desc, &ti, &tj)) return;
+    if (!XcdMap::tile(g, blockIdx.x, Mt, Nt, &ti, &tj)) return;
   } else {
     tj = blockIdx.x;
     ti = blockIdx.y;
@@ -138,87 +257,77 @@ void gemm_f64_kernel(GemmArgs g) {
   const int wm = wave % WAVES_M;
   const int wn = wave / WAVES_M;
 
-  d4_t acc[FM][FN];
+  constexpr int FC = WTN / 4;   // 4-column slices per wave (M4)
+  d4_t acc[M4 ? 1 : FM][M4 ? 1 : FN];
+  double acc4[M4 ? FM : 1][M4 ? FC : 1];
+  if (M4) {
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int c = 0; c < FC; ++c) acc4[a][c] = 0.0;
+  } else {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+  }
 
-  double ra[EA], rb[EB];
-
-  auto load = [&](int kt) {
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int idx = tid + e * NT;
-      int i, k;
-      if (!TRANS_A) { i = idx % BM; k = idx / BM; }
-      else          { k = idx % BK; i = idx / BK; }
-      int gi = i0 + i, gk = kt + k;
-      double val = 0.0;
-      if (gi < g.mvalid && gk < g.K)
-        val = TRANS_A ? g.A[(int64_t)gk + (int64_t)gi * g.lda] : g.A[(int64_t)gi + (int64_t)gk * g.lda];
-      ra[e] = val;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int idx = tid + e * NT;
-      int j, k;
-      if (!TRANS_B) { k = idx % BK; j = idx / BK; }
-      else          { j = idx % BN; k = idx / BN; }
-      int gj = j0 + j, gk = kt + k;
-      double val = 0.0;
-      if (gj < g.ncols && gk < g.K)
-        val = TRANS_B ? g.B[(int64_t)gj + (int64_t)gk * g.ldb] : g.B[(int64_t)gk + (int64_t)gj * g.ldb];
-      rb[e] = val;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int idx = tid + e * NT;
-      int i, k;
-      if (!TRANS_A) { i = idx % BM; k = idx / BM; }
-      else          { k = idx % BK; i = idx / BK; }
-      As[buf][k * SA + i] = ra[e];
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int idx = tid + e * NT;
-      int j, k;
-      if (!TRANS_B) { k = idx % BK; j = idx / BK; }
-      else          { j = idx % BN; k = idx / BN; }
-      Bs[buf][k * SB + j] = rb[e];
-    }
-  };
-
+  St st;
   if (nk > 0) {
-    load(klo);
-    store(0);
+    st.load(g, i0, j0, klo, tid);
+    st.store(As[0], Bs[0], tid);
     __syncthreads();
     for (int it = 0; it < nk; ++it) {
       const int buf = it & 1;
-      if (it + 1 < nk) load(klo + (it + 1) * BK);
+      if (it + 1 < nk) st.load(g, i0, j0, klo + (it + 1) * BK, tid);
       const double* as = As[buf];
       const double* bs = Bs[buf];
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        double af[FM], bf[FN];
         const int kr = kk + (lane >> 4);
+        double af[FM];
 #pragma unroll
         for (int a = 0; a < FM; ++a) af[a] = as[kr * SA + wm * WTM + a * 16 + (lane & 15)];
+        if (M4) {
 #pragma unroll
-        for (int b = 0; b < FN; ++b) bf[b] = bs[kr * SB + wn * WTN + b * 16 + (lane & 15)];
+          for (int c = 0; c < FC; ++c) {
+            const double bf = bs[kr * SB + wn * WTN + c * 4 + (lane & 3)];
 #pragma unroll
-        for (int a = 0; a < FM; ++a)
+            for (int a = 0; a < FM; ++a) acc4[a][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf, acc4[a][c], 0, 0, 0);
+          }
+        } else {
+          double bf[FN];
 #pragma unroll
-          for (int b = 0; b < FN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < FN; ++b) bf[b] = bs[kr * SB + wn * WTN + b * 16 + (lane & 15)];
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
       }
-      if (it + 1 < nk) store(buf ^ 1);
+      if (it + 1 < nk) st.store(As[buf ^ 1], Bs[buf ^ 1], tid);
       __syncthreads();
     }
   }
 
+  if (M4) {
+    // lane holds C[4 * ((lane >> 2) & 3) + (lane >> 4)][lane & 3] of each 16 x 4 slice
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int i = i0 + wm * WTM + a * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+      if (i >= g.mvalid) continue;
+#pragma unroll
+      for (int c = 0; c < FC; ++c) {
+        const int j = j0 + wn * WTN + c * 4 + (lane & 3);
+        if (j >= g.ncols) continue;
+        double val = g.alpha * acc4[a][c];
+        if (g.beta != 0.0) val += g.beta * g.Cin[(int64_t)i + (int64_t)j * g.ldcin];
+        g.C[(int64_t)i + (int64_t)j * g.ldc] = val;
+      }
+    }
+    return;
+  }
   // epilogue: lane holds rows q, q+4, q+8, q+12 (q = lane / 16) of one column
 #pragma unroll
   for (int a = 0; a < FM; ++a) {
@@ -237,6 +346,18 @@ void gemm_f64_kernel(GemmArgs g) {
       }
     }
   }
+}
+
+// Whether the chunked (VEC) loader may be used for these arguments.
+inline bool gemm_vec_ok(const GemmArgs& g, bool ta, bool tb) {
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  if (!al16(g.A) || !al16(g.B) || (g.lda & 1) || (g.ldb & 1)) return false;
+  // chunks run along i for A (no transpose) or k (transpose); along k for B
+  // (no transpose) or j (transpose): the run's bound must be a multiple of 8
+  if (!ta && (g.mvalid % 8)) return false;
+  if ((ta || !tb) && (g.K % 8)) return false;
+  if (tb && (g.ncols % 8)) return false;
+  return true;
 }
 
 }  // namespace gls

@@ -61,68 +61,66 @@ __global__ void pack_covariates_kernel(double* __restrict__ Wp, int N, int n, in
   }
 }
 
-// One diagonal block of the blocked factorization, entirely in LDS:
-//   Cholesky (right-looking, one column per step) of the NB_LEAF x NB_LEAF
-//   lower block at A (ld), then its inverse by column-wise forward
-//   substitution.  Writes the factor (zero upper part) back to A and the
-//   inverse (zero upper part) to Ainv (ld).  A non-positive or NaN pivot
-//   sets *info = row0 + j + 1 if *info is still 0 (the 1-based global pivot;
-//   blocks are processed in order so the first failure wins).
+// One diagonal block of the blocked factorization, entirely on chip:
+//   Cholesky of the NB_LEAF x NB_LEAF lower block at A (ld), right-looking with
+//   one barrier per column (the trailing update uses the unscaled column and
+//   the pivot, so column j is never rewritten in its own step), then the
+//   inverse of the factor by forward substitution with one lane per column
+//   and the column held in registers.  Writes the factor (zero upper part)
+//   back to A and the inverse (zero upper part) to Ainv (ld).  A non-positive
+//   or NaN pivot sets *info = row0 + j + 1 if *info is still 0 (the 1-based
+//   global pivot; blocks run in order, so the first failure wins).
 __global__ __launch_bounds__(256) void leaf_potrf_trtri_kernel(double* __restrict__ A, double* __restrict__ Ainv,
                                                                int64_t ld, int row0, int* __restrict__ info) {
   constexpr int B = NB_LEAF;
   constexpr int S = B + 1;
-  __shared__ double a[B * S];   // a[i + j * S] = A[i][j]
-  __shared__ double x[B * S];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < B * B; idx += blockDim.x) {
-    int i = idx % B, j = idx / B;
-    a[i + j * S] = (i >= j) ? A[(int64_t)i + (int64_t)j * ld] : 0.0;
+  static_assert(B == 64, "one lane per column of the block");
+  __shared__ double a[B * S];   // working copy, a[i + k * S] = A[i][k]
+  __shared__ double l[B * S];   // factor, row-major: l[i * S + k] = L[i][k]
+  const int t = threadIdx.x;
+  for (int idx = t; idx < B * B; idx += blockDim.x) {
+    const int i = idx % B, k = idx / B;
+    a[i + k * S] = (i >= k) ? A[(int64_t)i + (int64_t)k * ld] : 0.0;
+    l[i * S + k] = 0.0;
   }
-  if (tid == 0) bad = 0;
   __syncthreads();
+  const int kc = t & (B - 1);
+  const int r0 = t >> 6;
+  bool failed = false;
   for (int j = 0; j < B; ++j) {
-    if (tid == 0) {
-      double d = a[j + j * S];
-      if (!(d > 0.0)) {
-        if (!bad) {
-          bad = 1;
-          if (*info == 0) *info = row0 + j + 1;
-        }
-      }
-      a[j + j * S] = sqrt(d);
+    const double piv = a[j + j * S];
+    if (t == 0 && !failed && !(piv > 0.0)) {
+      failed = true;
+      if (*info == 0) *info = row0 + j + 1;
     }
-    __syncthreads();
-    const double djj = a[j + j * S];
-    for (int i = j + 1 + tid; i < B; i += blockDim.x) a[i + j * S] /= djj;
-    __syncthreads();
-    const int w = B - j - 1;
-    for (int idx = tid; idx < w * w; idx += blockDim.x) {
-      int ii = j + 1 + idx % w;
-      int kk = j + 1 + idx / w;
-      if (ii >= kk) a[ii + kk * S] -= a[ii + j * S] * a[kk + j * S];
+    if (t < B && t >= j) {
+      const double d = sqrt(piv);
+      l[t * S + j] = (t == j) ? d : a[t + j * S] / d;
+    }
+    if (kc > j) {
+      const double lk = a[kc + j * S] / piv;
+      for (int i = kc + r0; i < B; i += 4) a[i + kc * S] -= a[i + j * S] * lk;
     }
     __syncthreads();
   }
-  // inverse: column jj of X solves L x = e_jj (one thread per column)
-  if (tid < B) {
-    const int jj = tid;
+  if (t < B) {
+    const int jj = t;
+    double x[B];
+#pragma unroll
     for (int i = 0; i < B; ++i) {
-      double v = 0.0;
-      if (i >= jj) {
-        double s = (i == jj) ? 1.0 : 0.0;
-        for (int k = jj; k < i; ++k) s -= a[i + k * S] * x[k + jj * S];
-        v = s / a[i + i * S];
-      }
-      x[i + jj * S] = v;
+      double s = (i == jj) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= l[i * S + k] * x[k];
+      x[i] = (i >= jj) ? s / l[i * S + i] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < B; ++i) a[i + jj * S] = x[i];
   }
   __syncthreads();
-  for (int idx = tid; idx < B * B; idx += blockDim.x) {
-    int i = idx % B, j = idx / B;
-    A[(int64_t)i + (int64_t)j * ld] = (i >= j) ? a[i + j * S] : 0.0;
-    Ainv[(int64_t)i + (int64_t)j * ld] = (i >= j) ? x[i + j * S] : 0.0;
+  for (int idx = t; idx < B * B; idx += blockDim.x) {
+    const int i = idx % B, k = idx / B;
+    A[(int64_t)i + (int64_t)k * ld] = (i >= k) ? l[i * S + k] : 0.0;
+    Ainv[(int64_t)i + (int64_t)k * ld] = a[i + k * S];
   }
 }
 
