@@ -12,6 +12,7 @@
 #include "gemm_f64.hpp"
 #include "gls.h"
 #include "gls_internal.hpp"
+#include "lp_gemm.hpp"
 #include "setup_kernels.hpp"
 #include "snp_kernels.hpp"
 
@@ -87,6 +88,15 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   pl->off_os2 = take(sizeof(double) * bc);
   pl->off_ov = take(sizeof(double) * bc);
   pl->off_ost = take(sizeof(int32_t) * bc);
+  pl->bcp = (bc + 63) / 64 * 64;
+  pl->lp_bytes = o->precision == GLS_FP32_IR ? 4 : (o->precision == GLS_FP64 ? 0 : 2);
+  if (pl->lp_bytes) {
+    pl->off_Llp = take((size_t)pl->lp_bytes * N * N);
+    pl->off_Blp = take((size_t)pl->lp_bytes * N * pl->bcp);
+    pl->off_R = take(sizeof(double) * N * pl->bcp);
+    pl->off_cs = take(sizeof(double) * pl->bcp);
+    pl->off_red = take(sizeof(double) * 2048);
+  }
   pl->total = off;
   return true;
 }
@@ -334,6 +344,14 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   hipLaunchKernelGGL(form_m_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->L, (int)N, (int)n, Phi, ld_phi, h2);
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Linv, N * N, 0.0);
   chol_inv_rec(c, 0, (int)(N / NB_LEAF), s);
+  if (pl.lp_bytes) {
+    c->Llp = ws + pl.off_Llp;
+    c->Blp = ws + pl.off_Blp;
+    c->R = reinterpret_cast<double*>(ws + pl.off_R);
+    c->cs = reinterpret_cast<double*>(ws + pl.off_cs);
+    c->red = reinterpret_cast<double*>(ws + pl.off_red);
+    prepare_low_precision(c, s);
+  }
   // [X~_L | y~] = L^-1 [X_L | y]
   double* Wp = c->Xt;
   hipLaunchKernelGGL(pack_covariates_kernel, dim3(grid_for(N * p)), dim3(256), 0, s, Wp, (int)N, (int)n, (int)p, XL,
@@ -473,9 +491,106 @@ PhaseTimer::~PhaseTimer() {
   }
 }
 
+// Power-of-two target magnitude of the low-precision operands (FP16 has a
+// narrow exponent range: fill it; FP32 and BF16 need no range adjustment).
+static double lp_target(int precision) { return precision == GLS_FP16_IR ? 16384.0 : 1.0; }
+
+// Setup for the mixed forms: the low-precision copy of L^-1 (row-major,
+// scaled by a power of two recorded in red[0]) and zero padding rows of R.
+void prepare_low_precision(Ctx* c, hipStream_t s) {
+  const int64_t N = c->N;
+  double* part = c->red + 8;
+  hipLaunchKernelGGL(maxabs_kernel, dim3(1024), dim3(256), 0, s, c->Linv, N * N, part);
+  hipLaunchKernelGGL(maxabs_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)1024, part + 1024);
+  const double tgt = lp_target(c->opts.precision);
+  const int g = grid_for(N * N);
+  switch (c->opts.precision) {
+    case GLS_FP32_IR:
+      hipLaunchKernelGGL(convert_factor_kernel<float>, dim3(g), dim3(256), 0, s, c->Linv, (int)N,
+                         static_cast<float*>(c->Llp), part + 1024, tgt, c->red);
+      break;
+    case GLS_FP16_IR:
+      hipLaunchKernelGGL(convert_factor_kernel<_Float16>, dim3(g), dim3(256), 0, s, c->Linv, (int)N,
+                         static_cast<_Float16*>(c->Llp), part + 1024, tgt, c->red);
+      break;
+    default:
+      hipLaunchKernelGGL(convert_factor_kernel<__bf16>, dim3(g), dim3(256), 0, s, c->Linv, (int)N,
+                         static_cast<__bf16*>(c->Llp), part + 1024, tgt, c->red);
+      break;
+  }
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * c->plan.bcp)), dim3(256), 0, s, c->R, N * c->plan.bcp, 0.0);
+}
+
+template <typename T>
+static void lp_solve_t(Ctx* c, const double* src, int64_t lds, int mb, double beta, hipStream_t s) {
+  const int64_t N = c->N;
+  T* Blp = static_cast<T*>(c->Blp);
+  hipLaunchKernelGGL(scale_convert_kernel<T>, dim3((mb + 3) / 4), dim3(256), 0, s, src, lds, (int)c->n, (int)N, mb,
+                     Blp, N, lp_target(c->opts.precision), (const double*)c->red, c->cs);
+  LpArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.A = c->Llp;
+  a.lda = N;
+  a.B = Blp;
+  a.ldb = N;
+  a.Cin = c->Xt;
+  a.ldcin = N;
+  a.C = c->Xt;
+  a.ldc = N;
+  a.cscale = c->cs;
+  a.M = (int)N;
+  a.mvalid = (int)N;
+  a.ncols = mb;
+  a.K = (int)N;
+  a.beta = beta;
+  a.map_gm = 1;
+  a.map_gn = 16;
+  a.map_desc = 1;
+  const int Mt = (int)(N / 64), Nt = (mb + 63) / 64;
+  GemmArgs m{};
+  m.map_gm = 1;
+  m.map_gn = 16;
+  hipLaunchKernelGGL(lp_gemm_kernel<T>, dim3(XcdMap::grid(m, Mt, Nt)), dim3(256), 0, s, a);
+}
+
+// Xt (N x mb) = L^-1 src in the handle's low precision with FP32 accumulation;
+// beta = 1 adds to the current Xt (a refinement correction).
+static void lp_solve(Ctx* c, const double* src, int64_t lds, int mb, double beta, hipStream_t s) {
+  switch (c->opts.precision) {
+    case GLS_FP32_IR: lp_solve_t<float>(c, src, lds, mb, beta, s); break;
+    case GLS_FP16_IR: lp_solve_t<_Float16>(c, src, lds, mb, beta, s); break;
+    default: lp_solve_t<__bf16>(c, src, lds, mb, beta, s); break;
+  }
+}
+
+// R (rows < n) = X - L Xt in FP64 (the refinement residual).
+static void residual_fp64(Ctx* c, const double* X, int64_t ldx, int mb, hipStream_t s) {
+  GemmArgs g = gemm_args(c->L, c->N, c->Xt, c->N, c->R, c->N, (int)c->n, mb, (int)c->n, -1.0);
+  g.Cin = X;
+  g.ldcin = ldx;
+  g.beta = 1.0;
+  g.a_tri = TRI_LOWER;
+  g.a_diag = 0;
+  g.map_desc = 1;
+  gemm(false, false, true, g, s);
+}
+
 gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double* b, int64_t ld_b, double* s2,
                          double* v, int* st, hipStream_t s) {
-  {
+  if (c->plan.lp_bytes) {
+    {
+      PhaseTimer t(c, PH_WHITEN, s);
+      lp_solve(c, XR, ld_xr, mb, 0.0, s);
+    }
+    for (int sweep = 0; sweep < c->opts.refine_sweeps; ++sweep) {
+      {
+        PhaseTimer t(c, PH_RESIDUAL, s);
+        residual_fp64(c, XR, ld_xr, mb, s);
+      }
+      PhaseTimer t(c, PH_WHITEN, s);
+      lp_solve(c, c->R, c->N, mb, 1.0, s);
+    }
+  } else {
     PhaseTimer t(c, PH_WHITEN, s);
     whiten_fp64(c, XR, ld_xr, mb, c->Xt, s);
   }

@@ -21,6 +21,10 @@ struct Plan {
   size_t off_L = 0, off_Linv = 0, off_W = 0, off_Xt = 0;
   size_t off_buf0 = 0, off_buf1 = 0;
   size_t off_ob = 0, off_os2 = 0, off_ov = 0, off_ost = 0;
+  // mixed precision
+  int lp_bytes = 0;          // element size of the low-precision type (0: plain FP64)
+  int64_t bcp = 0;           // block columns rounded up to the tile width
+  size_t off_Llp = 0, off_Blp = 0, off_R = 0, off_cs = 0, off_red = 0;
   size_t total = 0;
 };
 
@@ -46,6 +50,12 @@ struct gls_ctx {
   double* os2 = nullptr;
   double* ov = nullptr;
   int* ost = nullptr;
+  // mixed precision (precision != GLS_FP64)
+  void* Llp = nullptr;      // N x N row-major low-precision L^-1 * 2^e
+  void* Blp = nullptr;      // N x bcp low-precision right-hand sides
+  double* R = nullptr;      // N x bcp FP64 refinement residuals
+  double* cs = nullptr;     // bcp per-column scale factors
+  double* red = nullptr;    // [0]: 2^-e of the factor; [8..]: reduction scratch
   hipEvent_t ev_copy[2] = {nullptr, nullptr};
   hipEvent_t ev_comp[2] = {nullptr, nullptr};
   // phase timing (gls_profile_*)
@@ -85,6 +95,7 @@ int64_t padded_n(int64_t n);
 bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl);
 
 void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, double* Xt, hipStream_t s);
+void prepare_low_precision(Ctx* c, hipStream_t s);
 void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,
                       hipStream_t s);
 gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double* b, int64_t ld_b, double* s2,
