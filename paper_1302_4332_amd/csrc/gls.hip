@@ -11,6 +11,7 @@
 
 #include "gemm_f64.hpp"
 #include "gls.h"
+#include "adjoint_kernels.hpp"
 #include "gls_internal.hpp"
 #include "lp_gemm.hpp"
 #include "setup_kernels.hpp"
@@ -96,6 +97,21 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
     pl->off_R = take(sizeof(double) * N * pl->bcp);
     pl->off_cs = take(sizeof(double) * pl->bcp);
     pl->off_red = take(sizeof(double) * 2048);
+  }
+  if (o->flags & GLS_KEEP_FOR_GRAD) {
+    const int64_t nc = adj_nc(p);
+    pl->off_Phi = take(sizeof(double) * N * N);
+    pl->off_Lbar = take(sizeof(double) * N * N);
+    pl->off_T1 = take(sizeof(double) * N * N);
+    pl->off_T2 = take(sizeof(double) * N * N);
+    pl->off_Xtb = take(sizeof(double) * N * pl->bcp);
+    pl->off_Xb = take(sizeof(double) * N * pl->bcp);
+    pl->off_Cb = take(sizeof(double) * p * pl->bcp);
+    pl->off_eb = take(sizeof(double) * pl->bcp);
+    pl->off_ct = take(sizeof(double) * nc * pl->bcp);
+    pl->off_Wb = take(sizeof(double) * N * p);
+    pl->off_W0b = take(sizeof(double) * N * p);
+    pl->off_acc = take(sizeof(double) * (nc + 2048));
   }
   pl->total = off;
   return true;
@@ -352,6 +368,23 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
     c->red = reinterpret_cast<double*>(ws + pl.off_red);
     prepare_low_precision(c, s);
   }
+  if (opts->flags & GLS_KEEP_FOR_GRAD) {
+    c->grad = true;
+    c->Phi = reinterpret_cast<double*>(ws + pl.off_Phi);
+    c->Lbar = reinterpret_cast<double*>(ws + pl.off_Lbar);
+    c->T1 = reinterpret_cast<double*>(ws + pl.off_T1);
+    c->T2 = reinterpret_cast<double*>(ws + pl.off_T2);
+    c->Xtb = reinterpret_cast<double*>(ws + pl.off_Xtb);
+    c->Xb = reinterpret_cast<double*>(ws + pl.off_Xb);
+    c->Cb = reinterpret_cast<double*>(ws + pl.off_Cb);
+    c->eb = reinterpret_cast<double*>(ws + pl.off_eb);
+    c->ct = reinterpret_cast<double*>(ws + pl.off_ct);
+    c->Wb = reinterpret_cast<double*>(ws + pl.off_Wb);
+    c->W0b = reinterpret_cast<double*>(ws + pl.off_W0b);
+    c->acc = reinterpret_cast<double*>(ws + pl.off_acc);
+    hipLaunchKernelGGL(keep_phi_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Phi, (int)N, (int)n, Phi, ld_phi);
+    reset_adjoint(c, s);
+  }
   // [X~_L | y~] = L^-1 [X_L | y]
   double* Wp = c->Xt;
   hipLaunchKernelGGL(pack_covariates_kernel, dim3(grid_for(N * p)), dim3(256), 0, s, Wp, (int)N, (int)n, (int)p, XL,
@@ -603,15 +636,180 @@ gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double
 
 }  // namespace gls
 
-extern "C" gls_status gls_backward_block(gls_handle h, int32_t, const double*, int64_t, const double*, const double*,
-                                         const double*, double*, void*) {
-  (void)h;
-  set_err("gls_backward_block: the adjoint is not available in this build");
-  return GLS_ERR_STATE;
+namespace gls {
+
+void reset_adjoint(Ctx* c, hipStream_t s) {
+  const int64_t N = c->N;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Lbar, N * N, 0.0);
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * c->p)), dim3(256), 0, s, c->Wb, N * c->p, 0.0);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, s, c->acc, (int64_t)adj_nc(c->p), 0.0);
 }
 
-extern "C" gls_status gls_backward_finish(gls_handle h, double*, double*, void*) {
-  (void)h;
-  set_err("gls_backward_finish: the adjoint is not available in this build");
-  return GLS_ERR_STATE;
+template <int P>
+static void adjoint_snp_p(Ctx* c, int mb, const double* bbar, const double* s2bar, const double* vbar,
+                          hipStream_t s) {
+  const int grid = (mb + SNP_PER_WG - 1) / SNP_PER_WG;
+  hipLaunchKernelGGL(snp_adjoint_kernel<P>, dim3(grid), dim3(64 * SNP_WAVES), 0, s, c->Xt, (int64_t)c->N, (int)c->N,
+                     mb, c->W, c->small, (int)c->n, bbar, (int64_t)P, s2bar, vbar, c->Cb, c->eb, c->ct);
+  hipLaunchKernelGGL(reduce_contrib_kernel, dim3(1), dim3(256), 0, s, c->ct, adj_nc(P), mb, c->acc);
+  hipLaunchKernelGGL(xtbar_kernel<P>, dim3(grid_for(c->N * mb)), dim3(256), 0, s, c->W, c->Xt, c->Cb, c->eb,
+                     (int)c->N, mb, c->Xtb);
+}
+
+template <int P>
+static void wbar_shared_p(Ctx* c, hipStream_t s) {
+  hipLaunchKernelGGL(wbar_shared_kernel<P>, dim3(grid_for(c->N)), dim3(256), 0, s, c->W, c->acc, (int)c->N, c->Wb);
+}
+
+#define GLS_P_SWITCH(p, CALL)                                                                          \
+  switch (p) {                                                                                         \
+    case 1: CALL(1); break; case 2: CALL(2); break; case 3: CALL(3); break; case 4: CALL(4); break;     \
+    case 5: CALL(5); break; case 6: CALL(6); break; case 7: CALL(7); break; case 8: CALL(8); break;     \
+    case 9: CALL(9); break; case 10: CALL(10); break; case 11: CALL(11); break; case 12: CALL(12); break; \
+    case 13: CALL(13); break; case 14: CALL(14); break; case 15: CALL(15); break; case 16: CALL(16); break; \
+    case 17: CALL(17); break; case 18: CALL(18); break; case 19: CALL(19); break; case 20: CALL(20); break; \
+    default: break;                                                                                    \
+  }
+
+// X~ of a block again (the adjoint recomputes instead of storing X~_R).
+static void recompute_whitened(Ctx* c, int mb, const double* XR, int64_t ld_xr, hipStream_t s) {
+  if (c->plan.lp_bytes) {
+    lp_solve(c, XR, ld_xr, mb, 0.0, s);
+    for (int sweep = 0; sweep < c->opts.refine_sweeps; ++sweep) {
+      residual_fp64(c, XR, ld_xr, mb, s);
+      lp_solve(c, c->R, c->N, mb, 1.0, s);
+    }
+  } else {
+    whiten_fp64(c, XR, ld_xr, mb, c->Xt, s);
+  }
+}
+
+gls_status block_backward(Ctx* c, int mb, const double* XR, int64_t ld_xr, const double* bbar, const double* s2bar,
+                          const double* vbar, double* XR_grad, hipStream_t s) {
+  const int64_t N = c->N;
+  PhaseTimer t(c, PH_BACKWARD, s);
+  recompute_whitened(c, mb, XR, ld_xr, s);
+#define GLS_ADJ(P) adjoint_snp_p<P>(c, mb, bbar, s2bar, vbar, s)
+  GLS_P_SWITCH(c->p, GLS_ADJ)
+#undef GLS_ADJ
+  {  // Wbar += X~_R Cbar^T   (op(B)[k][j] = Cbar[j + k p])
+    GemmArgs g = gemm_args(c->Xt, N, c->Cb, c->p, c->Wb, N, (int)N, c->p, mb, 1.0);
+    g.beta = 1.0;
+    gemm(false, true, false, g, s);
+  }
+  {  // X_R bar = L^-T X~_R bar   (op(A) = (L^-1)^T, upper: non-zero for k >= i)
+    GemmArgs g = gemm_args(c->Linv, N, c->Xtb, N, c->Xb, N, (int)N, mb, (int)N, 1.0);
+    g.a_tri = TRI_UPPER;
+    g.a_diag = 0;
+    g.map_desc = 0;
+    gemm(true, false, true, g, s);
+  }
+  if (XR_grad)
+    hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(c->n * mb)), dim3(256), 0, s, XR_grad, ld_xr, c->Xb, N, (int)c->n,
+                       mb);
+  {  // Lbar -= X_R bar X~_R^T   (lower tiles; op(B)[k][j] = X~[j + k N])
+    GemmArgs g = gemm_args(c->Xb, N, c->Xt, N, c->Lbar, N, (int)N, (int)N, mb, -1.0);
+    g.beta = 1.0;
+    g.c_lower = 1;
+    g.c_diag = 0;
+    gemm(false, true, false, g, s);
+  }
+  return GLS_OK;
+}
+
+gls_status finish_backward(Ctx* c, double* y_grad, double* h2_grad, hipStream_t s) {
+  const int64_t N = c->N;
+  const int p = c->p;
+  PhaseTimer t(c, PH_BACKWARD, s);
+#define GLS_WB(P) wbar_shared_p<P>(c, s)
+  GLS_P_SWITCH(p, GLS_WB)
+#undef GLS_WB
+  {  // [X_L | y] bar = L^-T [X~_L | y~] bar
+    GemmArgs g = gemm_args(c->Linv, N, c->Wb, N, c->W0b, N, (int)N, p, (int)N, 1.0);
+    g.a_tri = TRI_UPPER;
+    g.a_diag = 0;
+    gemm(true, false, false, g, s);
+  }
+  if (y_grad)
+    hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(c->n)), dim3(256), 0, s, y_grad, c->n, c->W0b + (int64_t)(p - 1) * N,
+                       N, (int)c->n, 1);
+  {  // Lbar -= [X_L | y]bar [X~_L | y~]^T
+    GemmArgs g = gemm_args(c->W0b, N, c->W, N, c->Lbar, N, (int)N, (int)N, p, -1.0);
+    g.beta = 1.0;
+    g.c_lower = 1;
+    g.c_diag = 0;
+    gemm(false, true, false, g, s);
+  }
+  const int gN = grid_for(N * N);
+  hipLaunchKernelGGL(lower_part_kernel, dim3(gN), dim3(256), 0, s, c->Lbar, (int)N, 0);
+  {  // T1 = lower part of L^T Lbar   (op(A) = L^T upper, op(B) = Lbar lower)
+    GemmArgs g = gemm_args(c->L, N, c->Lbar, N, c->T1, N, (int)N, (int)N, (int)N, 1.0);
+    g.a_tri = TRI_UPPER;
+    g.a_diag = 0;
+    g.b_tri = TRI_LOWER;
+    g.b_diag = 0;
+    g.c_lower = 1;
+    g.c_diag = 0;
+    gemm(true, false, false, g, s);
+  }
+  hipLaunchKernelGGL(lower_part_kernel, dim3(gN), dim3(256), 0, s, c->T1, (int)N, 1);
+  {  // T2 = T1 L^-1   (lower x lower = lower)
+    GemmArgs g = gemm_args(c->T1, N, c->Linv, N, c->T2, N, (int)N, (int)N, (int)N, 1.0);
+    g.a_tri = TRI_LOWER;
+    g.a_diag = 0;
+    g.b_tri = TRI_LOWER;
+    g.b_diag = 0;
+    g.c_lower = 1;
+    g.c_diag = 0;
+    gemm(false, false, false, g, s);
+  }
+  {  // T1 = L^-T T2   (the adjoint of M, up to symmetrisation)
+    GemmArgs g = gemm_args(c->Linv, N, c->T2, N, c->T1, N, (int)N, (int)N, (int)N, 1.0);
+    g.a_tri = TRI_UPPER;
+    g.a_diag = 0;
+    g.b_tri = TRI_LOWER;
+    g.b_diag = 0;
+    gemm(true, false, false, g, s);
+  }
+  double* part = c->acc + adj_nc(p);
+  hipLaunchKernelGGL(h2_contract_kernel, dim3(1024), dim3(256), 0, s, c->T1, c->Phi, (int)N, (int)c->n, part);
+  if (h2_grad) hipLaunchKernelGGL(sum_ordered_kernel, dim3(1), dim3(64), 0, s, part, 1024, h2_grad);
+  reset_adjoint(c, s);
+  return GLS_OK;
+}
+
+}  // namespace gls
+
+extern "C" gls_status gls_backward_block(gls_handle h, int32_t mb, const double* XR, int64_t ld_xr,
+                                         const double* b_bar, const double* sigma2_bar, const double* v_bar,
+                                         double* XR_grad, void* stream) {
+  Ctx* c = h;
+  if (!c || !c->ready || !c->grad) {
+    set_err("gls_backward_block: handle not set up with GLS_KEEP_FOR_GRAD");
+    return GLS_ERR_STATE;
+  }
+  if (mb < 0 || mb > c->bc) return arg_fail("gls_backward_block: mb must lie in [0, block_cols]");
+  if (mb == 0) return GLS_OK;
+  if (!XR || ld_xr < c->n) return arg_fail("gls_backward_block: XR is NULL or ld_xr < n");
+  if (!b_bar || !sigma2_bar || !v_bar) return arg_fail("gls_backward_block: NULL cotangent");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gls_status st = block_backward(c, mb, XR, ld_xr, b_bar, sigma2_bar, v_bar, XR_grad, s);
+  if (st != GLS_OK) return st;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "gls_backward_block: launch");
+  return GLS_OK;
+}
+
+extern "C" gls_status gls_backward_finish(gls_handle h, double* y_grad, double* h2_grad, void* stream) {
+  Ctx* c = h;
+  if (!c || !c->ready || !c->grad) {
+    set_err("gls_backward_finish: handle not set up with GLS_KEEP_FOR_GRAD");
+    return GLS_ERR_STATE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gls_status st = finish_backward(c, y_grad, h2_grad, s);
+  if (st != GLS_OK) return st;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "gls_backward_finish: launch");
+  return GLS_OK;
 }

@@ -25,6 +25,9 @@ struct Plan {
   int lp_bytes = 0;          // element size of the low-precision type (0: plain FP64)
   int64_t bcp = 0;           // block columns rounded up to the tile width
   size_t off_Llp = 0, off_Blp = 0, off_R = 0, off_cs = 0, off_red = 0;
+  // adjoint (GLS_KEEP_FOR_GRAD)
+  size_t off_Phi = 0, off_Lbar = 0, off_T1 = 0, off_T2 = 0, off_Xtb = 0, off_Xb = 0;
+  size_t off_Cb = 0, off_eb = 0, off_ct = 0, off_Wb = 0, off_W0b = 0, off_acc = 0;
   size_t total = 0;
 };
 
@@ -56,6 +59,20 @@ struct gls_ctx {
   double* R = nullptr;      // N x bcp FP64 refinement residuals
   double* cs = nullptr;     // bcp per-column scale factors
   double* red = nullptr;    // [0]: 2^-e of the factor; [8..]: reduction scratch
+  // adjoint state (GLS_KEEP_FOR_GRAD)
+  bool grad = false;
+  double* Phi = nullptr;    // N x N, lower triangle of Phi (zero padding)
+  double* Lbar = nullptr;   // N x N accumulated adjoint of L (lower part meaningful)
+  double* T1 = nullptr;     // N x N scratch of the Cholesky adjoint
+  double* T2 = nullptr;     // N x N scratch
+  double* Xtb = nullptr;    // N x bcp adjoint of X~_R of the current block
+  double* Xb = nullptr;     // N x bcp adjoint of X_R of the current block
+  double* Cb = nullptr;     // p x bcp per-SNP coefficients of x~bar on [X~_L | y~]
+  double* eb = nullptr;     // bcp per-SNP coefficient of x~bar on x~
+  double* ct = nullptr;     // nc x bcp per-SNP shared-term contributions
+  double* Wb = nullptr;     // N x p accumulated adjoint of [X~_L | y~]
+  double* W0b = nullptr;    // N x p adjoint of [X_L | y]
+  double* acc = nullptr;    // nc accumulated shared adjoints, then partial sums
   hipEvent_t ev_copy[2] = {nullptr, nullptr};
   hipEvent_t ev_comp[2] = {nullptr, nullptr};
   // phase timing (gls_profile_*)
@@ -96,6 +113,7 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl);
 
 void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, double* Xt, hipStream_t s);
 void prepare_low_precision(Ctx* c, hipStream_t s);
+void reset_adjoint(Ctx* c, hipStream_t s);
 void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,
                       hipStream_t s);
 gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double* b, int64_t ld_b, double* s2,

@@ -225,3 +225,70 @@ class GLSContext:
                               ctypes.byref(stats))
         _check(st)
         return (b, s2, v, status), stats
+
+
+class GLSFunction(torch.autograd.Function):
+    """(b, sigma2, v) of every SNP as a differentiable function of y, X_R and h2.
+
+    Forward runs the library's setup and block path; backward is the
+    library's hand-written adjoint (gls_backward_block per block, then
+    gls_backward_finish), which recomputes each block's whitened SNPs instead
+    of storing them.  Phi and X_L are constants.
+
+        b, sigma2, v = GLSFunction.apply(y, XR, h2, Phi, XL, block_cols, precision, sweeps)
+
+    y (n,), XR (m, n), Phi (n, n), XL (n, p-1): float64 CUDA tensors; h2 a
+    float64 scalar tensor.
+    """
+
+    @staticmethod
+    def forward(ctx, y, XR, h2, Phi, XL, block_cols, precision="fp64", sweeps=0):
+        g = GLSContext(Phi, float(h2), XL, y.detach().contiguous(), block_cols=block_cols, precision=precision,
+                       refine_sweeps=sweeps, keep_for_grad=True)
+        XRd = XR.detach().contiguous()
+        m = XRd.shape[0]
+        dev = XRd.device
+        b = torch.empty((m, g.p), dtype=torch.float64, device=dev)
+        s2 = torch.empty(m, dtype=torch.float64, device=dev)
+        v = torch.empty(m, dtype=torch.float64, device=dev)
+        st = torch.empty(m, dtype=torch.int32, device=dev)
+        for j0 in range(0, m, block_cols):
+            j1 = min(m, j0 + block_cols)
+            g.block_into(XRd[j0:j1], b[j0:j1], s2[j0:j1], v[j0:j1], st[j0:j1])
+        ctx.g = g
+        ctx.block_cols = block_cols
+        ctx.h2_shape = h2.shape if isinstance(h2, torch.Tensor) else ()
+        ctx.save_for_backward(XRd)
+        return b, s2, v
+
+    @staticmethod
+    def backward(ctx, bbar, s2bar, vbar):
+        g = ctx.g
+        (XR,) = ctx.saved_tensors
+        m, n = XR.shape
+        dev = XR.device
+        z = lambda shape: torch.zeros(shape, dtype=torch.float64, device=dev)
+        bbar = z((m, g.p)) if bbar is None else bbar.contiguous()
+        s2bar = z(m) if s2bar is None else s2bar.contiguous()
+        vbar = z(m) if vbar is None else vbar.contiguous()
+        want_xr = ctx.needs_input_grad[1]
+        XR_grad = torch.empty_like(XR) if want_xr else None
+        stream = _stream()
+        for j0 in range(0, m, ctx.block_cols):
+            j1 = min(m, j0 + ctx.block_cols)
+            st = lib().gls_backward_block(g.handle, j1 - j0, _ptr(XR[j0:j1]), n, _ptr(bbar[j0:j1]),
+                                          _ptr(s2bar[j0:j1]), _ptr(vbar[j0:j1]),
+                                          _ptr(XR_grad[j0:j1]) if want_xr else None, stream)
+            _check(st)
+        y_grad = torch.empty(n, dtype=torch.float64, device=dev)
+        h2_grad = torch.empty(1, dtype=torch.float64, device=dev)
+        _check(lib().gls_backward_finish(g.handle, _ptr(y_grad), _ptr(h2_grad), stream))
+        torch.cuda.current_stream().synchronize()
+        g.close()
+        ctx.g = None
+        return y_grad, XR_grad, h2_grad.reshape(ctx.h2_shape), None, None, None, None, None
+
+
+def t2_loss(b, sigma2, v):
+    """Sum over SNPs of squared t-statistics of the SNP coefficient."""
+    return (b[:, -1] ** 2 / (sigma2 * v)).sum()
