@@ -26,6 +26,21 @@ METRIC = "SNPs/sec (GLS solves/s) at n=10k,p=4; TRSM TFLOP/s vs MFMA peak"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32_ir": 157.3, "fp16_ir": 2500.0, "bf16_ir": 2500.0}
 
 
+# HBM traffic of the dominant kernel per full 8,192-SNP launch at n = 10,000, from
+# two rocprofv3 --pmc runs (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, factors
+# from a 1 GiB device copy; summary in profiles/).  Valid only while the
+# kernel source is the one those counters were taken on.
+TRAFFIC_RECORD = {"kernel_sha1": "c6711a338240005c", "n": 10000, "block_cols": 8192, "bytes_per_launch": 60.27e9}
+
+
+def kernel_hash() -> str:
+    import hashlib
+    a = open(os.path.join(ROOT, "paper_1302_4332_amd", "csrc", "gemm_f64.hpp"), "rb").read()
+    g = open(os.path.join(ROOT, "paper_1302_4332_amd", "csrc", "gls.hip")).read()
+    line = [l for l in g.splitlines() if l.startswith("constexpr int GBM")][0]
+    return hashlib.sha1(a + line.encode()).hexdigest()[:16]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -40,6 +55,83 @@ def blas_threads() -> int:
         return os.cpu_count() or 1
 
 
+def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
+    """Mixed-precision forms on the same workload, and the adjoint on the
+    n = 4,096 differentiation study; one timed study each."""
+    import torch
+
+    from oracle import gls_oracle as O
+    from paper_1302_4332_amd import synth
+    from paper_1302_4332_amd.gls import GLSContext, GLSFunction, t2_loss
+
+    w = st.w
+    n, p, bc, h2 = w.n, w.p, w.block_cols, w.h2
+    res = {}
+    # oracle on a sample of SNPs (first 512 and the ragged tail) for the error of each form
+    ost = O.Study(st.Phi, h2, st.XL, st.y)
+    samp = np.r_[np.arange(512), np.arange(m - 64, m)]
+    ref = ost.block(np.concatenate([st.snps(0, 512), st.snps(m - 64, m)]).T)
+    for prec, sweeps in (("fp32_ir", 1), ("fp16_ir", 3), ("bf16_ir", 4)):
+        b_d = torch.empty((m, p), dtype=torch.float64, device=dev)
+        s2_d = torch.empty(m, dtype=torch.float64, device=dev)
+        v_d = torch.empty(m, dtype=torch.float64, device=dev)
+        st_d = torch.empty(m, dtype=torch.int32, device=dev)
+
+        def study(profile):
+            ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec, refine_sweeps=sweeps)
+            if profile:
+                ctx.profile(True)
+            for j0 in range(0, m, bc):
+                j1 = min(m, j0 + bc)
+                ctx.block_into(X_d[j0:j1], b_d[j0:j1], s2_d[j0:j1], v_d[j0:j1], st_d[j0:j1])
+            ph = ctx.profile_read() if profile else None
+            ctx.close()
+            return ph
+
+        study(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph = study(True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        g = b_d.cpu().numpy()[samp]
+        ok = ref["status"] == 0
+        err = np.max(np.abs(g[ok] - ref["b"][ok]), axis=1) / np.max(np.abs(ref["b"][ok]), axis=1)
+        lp_ms, res_ms = ph["whiten"][1], ph["residual"][1]
+        lp_flops = float(n) * n * m * (1 + sweeps)
+        r_flops = float(n) * n * m * sweeps
+        res[f"{prec}_{sweeps}sweeps"] = {
+            "snps_per_s": m / (ms / 1e3), "ms_per_study": ms, "max_rel_err_b_sampled": float(err.max()),
+            "lowp_tflops": lp_flops / (lp_ms / 1e3) / 1e12, "lowp_peak": PEAK_TFLOPS[prec],
+            "fp64_residual_tflops": (r_flops / (res_ms / 1e3) / 1e12) if res_ms else None,
+            "phases_ms": {k: v[1] for k, v in ph.items()}}
+        log(f"{prec} x{sweeps}: {m / (ms / 1e3):,.0f} SNPs/s, max rel err {err.max():.2e}")
+        del b_d, s2_d, v_d, st_d
+    # adjoint on the differentiation study
+    w3 = synth.WORKLOADS["c3_grad_n4096"]
+    s3 = synth.make_study(w3)
+    X3 = torch.tensor(s3.snps(0, w3.m), device=dev)
+    Phi3, XL3, y3 = (torch.tensor(a, device=dev) for a in (s3.Phi, s3.XL, s3.y))
+    for prec, sweeps in (("fp64", 0), ("fp32_ir", 2)):
+        def fwd_bwd():
+            yt = y3.clone().requires_grad_(True)
+            Xt = X3.clone().requires_grad_(True)
+            h2t = torch.tensor(w3.h2, dtype=torch.float64, device=dev, requires_grad=True)
+            b, s2, v = GLSFunction.apply(yt, Xt, h2t, Phi3, XL3, w3.block_cols, prec, sweeps)
+            t2_loss(b, s2, v).backward()
+            return h2t.grad
+        fwd_bwd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gh = fwd_bwd()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res[f"adjoint_c3_{prec}"] = {"workload": w3.name, "ms_fwd_bwd": ms, "snps_per_s": w3.m / (ms / 1e3),
+                                     "h2_grad": float(gh)}
+        log(f"adjoint {prec}: {ms:.1f} ms forward+backward")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,7 +143,10 @@ def main():
     ap.add_argument("--sweeps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192, help="SNPs the oracle solves for the CPU baseline")
-    ap.add_argument("--stream", action="store_true", help="also time the streamed path from pinned host memory")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streamed (pinned host memory) measurement")
+    ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision and adjoint measurements")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM traffic counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -84,6 +179,14 @@ def main():
         X_d[j0:j1] = torch.from_numpy(synth.genotypes_u8(n, j0, j1, w.seed)).to(dev).to(torch.float64)
     torch.cuda.synchronize()
     log(f"SNP matrix resident in HBM ({X_d.numel() * 8 / 1e9:.1f} GB) after {time.perf_counter() - t:.1f}s")
+
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy of 1 GiB done")
 
     b_d = torch.empty((m, p), dtype=torch.float64, device=dev)
     s2_d = torch.empty(m, dtype=torch.float64, device=dev)
@@ -139,8 +242,13 @@ def main():
     flops_per_step = float(n) * n * m
     achieved = flops_per_step * args.steps / (wms / 1e3) / 1e12 if wms > 0 else None
     peak = PEAK_TFLOPS[args.precision]
+    traffic = None
+    if (args.precision == "fp64" and kernel_hash() == TRAFFIC_RECORD["kernel_sha1"] and n == TRAFFIC_RECORD["n"]
+            and bc == TRAFFIC_RECORD["block_cols"]):
+        traffic = TRAFFIC_RECORD["bytes_per_launch"]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": (achieved / peak) if achieved else None, "traffic": None,
+                "frac": (achieved / peak) if achieved else None, "traffic": traffic,
+                "traffic_unit": "bytes per full 8,192-SNP launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE, calibrated)",
                 "kernel": "gemm_f64_kernel<64,64,16,1,4,false,false,MAP_XCD,VEC,M4> (X~ = L^-1 X)",
                 "launch_ms_avg": wms / wl if wl else None, "launches": wl,
                 "flops_per_snp": float(n) * n}
@@ -156,7 +264,9 @@ def main():
         "snps_per_s_excl_setup": m / ((ms_per_step - setup_ms) / 1e3) if ms_per_step > setup_ms else None,
     }
 
-    if args.stream:
+    if not args.no_forms:
+        out["forms"] = measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev)
+    if not args.no_stream:
         host = torch.empty((m, n), dtype=torch.float64).pin_memory()
         host.copy_(X_d)
         ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps)
@@ -165,7 +275,7 @@ def main():
         (_, _, _, _), stats = ctx.stream(host)
         out["stream"] = {"snps_per_s": m / (stats.wall_ms / 1e3), "wall_ms": stats.wall_ms,
                          "compute_ms": stats.compute_ms, "h2d_GBps": stats.h2d_bytes / (stats.wall_ms / 1e3) / 1e9,
-                         "blocks": stats.blocks}
+                         "blocks": stats.blocks, "note": "PCIe-inclusive: pinned host X_R, setup excluded"}
         ctx.close()
         del host
         log(f"streamed: {out['stream']['snps_per_s']:,.0f} SNPs/s")
