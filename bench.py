@@ -277,6 +277,12 @@ def main():
                          "compute_ms": stats.compute_ms, "h2d_GBps": stats.h2d_bytes / (stats.wall_ms / 1e3) / 1e9,
                          "blocks": stats.blocks, "note": "PCIe-inclusive: pinned host X_R, setup excluded"}
         ctx.close()
+        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps,
+                         serial_stream=True)
+        (_, _, _, _), ss = ctx.stream(host)
+        out["stream"]["serial_snps_per_s"] = m / (ss.wall_ms / 1e3)
+        out["stream"]["serial_wall_ms"] = ss.wall_ms
+        ctx.close()
         del host
         log(f"streamed: {out['stream']['snps_per_s']:,.0f} SNPs/s")
 

@@ -62,11 +62,19 @@ typedef enum {
   GLS_FP64 = 0,     /* plain FP64 MFMA                                           */
   GLS_FP32_IR = 1,  /* FP32 MFMA bulk + FP64 residual refinement sweeps          */
   GLS_FP16_IR = 2,  /* FP16 MFMA (power-of-two column scaling) + FP64 refinement */
-  GLS_BF16_IR = 3   /* BF16 MFMA (power-of-two column scaling) + FP64 refinement */
+  GLS_BF16_IR = 3,  /* BF16 MFMA (power-of-two column scaling) + FP64 refinement */
+  GLS_INT8_EMU = 4  /* byte dosages only (gls_block_u8 / gls_stream_u8): the product
+                       with L^-1 as eight exact int8 slice products on the integer
+                       matrix cores, combined in FP64 (FP64-level accuracy); FP64
+                       input on such a handle runs the plain FP64 product        */
 } gls_precision;
 
 /* gls_opts.flags: keep Phi and the factor terms needed by the adjoint. */
 #define GLS_KEEP_FOR_GRAD 1u
+/* gls_opts.flags: gls_stream without overlap (copy, solve and results one
+ * after another on the compute stream): the naive offloading pattern of the
+ * paper's Sec. 3, for comparison with the double-buffered default. */
+#define GLS_STREAM_SERIAL 2u
 
 typedef struct {
   int32_t precision;      /* gls_precision                                       */
@@ -109,6 +117,16 @@ gls_status gls_block(gls_handle h, int32_t mb, const double* XR, int64_t ld_xr,
                      double* b, int64_t ld_b, double* sigma2, double* v,
                      int32_t* snp_status, void* stream);
 
+/* One SNP block given as genotype bytes: G is n x mb uint8 (ld_g >= n),
+ * entries 0..127 (dosages 0, 1, 2).  Same outputs and asynchrony as
+ * gls_block.  With GLS_FP64 or the mixed forms the bytes are widened to FP64
+ * on the device and the results are bitwise those of gls_block on the same
+ * values; with GLS_INT8_EMU the product runs on the integer matrix cores
+ * (see gls_precision).  Moves 1 byte per sample instead of 8. */
+gls_status gls_block_u8(gls_handle h, int32_t mb, const uint8_t* G, int64_t ld_g,
+                        double* b, int64_t ld_b, double* sigma2, double* v,
+                        int32_t* snp_status, void* stream);
+
 /* Per-stream timing and byte counts filled by gls_stream (may be NULL). */
 typedef struct {
   int64_t blocks;        /* blocks processed                                  */
@@ -132,6 +150,14 @@ gls_status gls_stream(gls_handle h, int64_t m, int64_t col0,
                       double* b_host, double* sigma2_host, double* v_host,
                       int32_t* status_host, void* compute_stream, void* copy_stream,
                       gls_stream_stats* stats_out);
+
+/* gls_stream for genotype bytes: G_host is n x m uint8 (ld_g >= n) in
+ * page-locked host memory; blocks are processed as by gls_block_u8. */
+gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0,
+                         const uint8_t* G_host, int64_t ld_g,
+                         double* b_host, double* sigma2_host, double* v_host,
+                         int32_t* status_host, void* compute_stream, void* copy_stream,
+                         gls_stream_stats* stats_out);
 
 /* Adjoint of one SNP block (requires GLS_KEEP_FOR_GRAD at setup).
  * Given cotangents b_bar (p x mb, ld p), sigma2_bar (mb), v_bar (mb) of the

@@ -14,6 +14,7 @@
 #include "adjoint_kernels.hpp"
 #include "gls_internal.hpp"
 #include "lp_gemm.hpp"
+#include "ozaki_i8.hpp"
 #include "setup_kernels.hpp"
 #include "snp_kernels.hpp"
 
@@ -58,7 +59,7 @@ static int64_t recursion_temp_leaves(int a, int b) {
 
 bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   if (n < 2 || p < 1 || p > PMAX || n <= p || !o || o->block_cols < 1) return false;
-  if (o->precision < GLS_FP64 || o->precision > GLS_BF16_IR) return false;
+  if (o->precision < GLS_FP64 || o->precision > GLS_INT8_EMU) return false;
   if (o->refine_sweeps < 0 || o->refine_sweeps > 4) return false;
   if (n > (int64_t)1 << 20) return false;
   const int64_t N = padded_n(n);
@@ -90,7 +91,17 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   pl->off_ov = take(sizeof(double) * bc);
   pl->off_ost = take(sizeof(int32_t) * bc);
   pl->bcp = (bc + 63) / 64 * 64;
-  pl->lp_bytes = o->precision == GLS_FP32_IR ? 4 : (o->precision == GLS_FP64 ? 0 : 2);
+  pl->lp_bytes = o->precision == GLS_FP32_IR ? 4
+                 : (o->precision == GLS_FP16_IR || o->precision == GLS_BF16_IR) ? 2 : 0;
+  pl->off_ub0 = take((size_t)n * bc);
+  pl->off_ub1 = take((size_t)n * bc);
+  if (o->precision == GLS_INT8_EMU) {
+    pl->off_ubp = take((size_t)N * pl->bcp);
+    pl->off_sl = take((size_t)OZ_SLICES * N * N);
+    pl->off_ex = take(sizeof(int) * N);
+  } else {
+    pl->off_x64 = take(sizeof(double) * N * bc);
+  }
   if (pl->lp_bytes) {
     pl->off_Llp = take((size_t)pl->lp_bytes * N * N);
     pl->off_Blp = take((size_t)pl->lp_bytes * N * pl->bcp);
@@ -195,6 +206,9 @@ static int grid_for(int64_t total) {
 //                            L21 = A21 L11^-T,  A22 -= L21 L21^T
 //                            L22 = chol(A22),   L22^-1
 //                            (L^-1)21 = -L22^-1 L21 L11^-1
+// Large setup products use the XCD-aware heavy-first mapping; small ones the plain grid.
+static bool big_product(int rows, int cols) { return (int64_t)rows * cols >= (int64_t)1024 * 1024; }
+
 static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
   const int64_t N = c->N;
   double* L = c->L;
@@ -221,27 +235,29 @@ static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
     GemmArgs g = gemm_args(T, w2, Li11, N, A21, N, w2, w1, w1, 1.0);
     g.b_tri = TRI_UPPER;
     g.b_diag = 0;
-    gemm(false, true, false, g, s);
+    gemm(false, true, big_product(w2, w1), g, s);
   }
   {  // A22 -= L21 L21^T  (lower tiles)
     GemmArgs g = gemm_args(A21, N, A21, N, A22, N, w2, w2, w1, -1.0);
     g.beta = 1.0;
     g.c_lower = 1;
     g.c_diag = 0;
-    gemm(false, true, false, g, s);
+    g.map_desc = 1;
+    gemm(false, true, big_product(w2, w2), g, s);
   }
   chol_inv_rec(c, mid, b, s);
   {  // T = L21 L11^-1   (op(B) = Li11 lower: non-zero for k >= j)
     GemmArgs g = gemm_args(A21, N, Li11, N, T, w2, w2, w1, w1, 1.0);
     g.b_tri = TRI_LOWER;
     g.b_diag = 0;
-    gemm(false, false, false, g, s);
+    gemm(false, false, big_product(w2, w1), g, s);
   }
   {  // (L^-1)21 = -L22^-1 T   (op(A) = Li22 lower: non-zero for k <= i)
     GemmArgs g = gemm_args(Li22, N, T, w2, Li21, N, w2, w1, w2, -1.0);
     g.a_tri = TRI_LOWER;
     g.a_diag = 0;
-    gemm(false, false, false, g, s);
+    g.map_desc = 1;
+    gemm(false, false, big_product(w2, w1), g, s);
   }
 }
 
@@ -360,6 +376,18 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   hipLaunchKernelGGL(form_m_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->L, (int)N, (int)n, Phi, ld_phi, h2);
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Linv, N * N, 0.0);
   chol_inv_rec(c, 0, (int)(N / NB_LEAF), s);
+  c->ub[0] = reinterpret_cast<uint8_t*>(ws + pl.off_ub0);
+  c->ub[1] = reinterpret_cast<uint8_t*>(ws + pl.off_ub1);
+  if (opts->precision == GLS_INT8_EMU) {
+    c->ubp = reinterpret_cast<uint8_t*>(ws + pl.off_ubp);
+    c->sl = reinterpret_cast<int8_t*>(ws + pl.off_sl);
+    c->ex = reinterpret_cast<int*>(ws + pl.off_ex);
+    hipLaunchKernelGGL(row_exponent_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, c->Linv, (int)N, c->ex);
+    hipLaunchKernelGGL(slice_factor_kernel, dim3((unsigned)(N / 64), (unsigned)(N / 64)), dim3(256), 0, s, c->Linv,
+                       (int)N, (const int*)c->ex, c->sl);
+  } else {
+    c->x64 = reinterpret_cast<double*>(ws + pl.off_x64);
+  }
   if (pl.lp_bytes) {
     c->Llp = ws + pl.off_Llp;
     c->Blp = ws + pl.off_Blp;
@@ -471,6 +499,25 @@ gls_status gls_profile_read(gls_handle h, gls_phase_stats* out, int32_t reset) {
       c->prof_ms[i] = 0.0;
     }
   }
+  return GLS_OK;
+}
+
+gls_status gls_block_u8(gls_handle h, int32_t mb, const uint8_t* G, int64_t ld_g, double* b, int64_t ld_b,
+                        double* sigma2, double* v, int32_t* snp_status, void* stream) {
+  Ctx* c = h;
+  if (!c || !c->ready) {
+    set_err("gls_block_u8: handle is not set up");
+    return GLS_ERR_STATE;
+  }
+  if (mb < 0 || mb > c->bc) return arg_fail("gls_block_u8: mb must lie in [0, block_cols]");
+  if (mb == 0) return GLS_OK;
+  if (!G || ld_g < c->n) return arg_fail("gls_block_u8: G is NULL or ld_g < n");
+  if (!b || ld_b < c->p || !sigma2 || !v || !snp_status) return arg_fail("gls_block_u8: NULL output or ld_b < p");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gls_status st = block_forward_u8(c, mb, G, ld_g, b, ld_b, sigma2, v, snp_status, s);
+  if (st != GLS_OK) return st;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "gls_block_u8: launch");
   return GLS_OK;
 }
 
@@ -637,6 +684,36 @@ gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double
 }  // namespace gls
 
 namespace gls {
+
+gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, double* b, int64_t ld_b, double* s2,
+                            double* v, int* st, hipStream_t s) {
+  const int64_t N = c->N;
+  if (c->opts.precision == GLS_INT8_EMU) {
+    {
+      PhaseTimer t(c, PH_WHITEN, s);
+      hipLaunchKernelGGL(pack_u8_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->ubp);
+      OzArgs a;
+      a.A = c->sl;
+      a.ex = c->ex;
+      a.B = c->ubp;
+      a.C = c->Xt;
+      a.ldc = N;
+      a.N = (int)N;
+      a.ncols = mb;
+      a.map_gm = 1;
+      a.map_gn = 16;
+      GemmArgs m{};
+      m.map_gm = 1;
+      m.map_gn = 16;
+      hipLaunchKernelGGL(ozaki_i8_kernel, dim3(XcdMap::grid(m, (int)(N / 64), (mb + 63) / 64)), dim3(256), 0, s, a);
+    }
+    PhaseTimer t(c, PH_SNP, s);
+    snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
+    return GLS_OK;
+  }
+  hipLaunchKernelGGL(u8_to_f64_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->x64);
+  return block_forward(c, mb, c->x64, N, b, ld_b, s2, v, st, s);
+}
 
 void reset_adjoint(Ctx* c, hipStream_t s) {
   const int64_t N = c->N;

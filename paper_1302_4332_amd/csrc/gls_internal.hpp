@@ -25,6 +25,8 @@ struct Plan {
   int lp_bytes = 0;          // element size of the low-precision type (0: plain FP64)
   int64_t bcp = 0;           // block columns rounded up to the tile width
   size_t off_Llp = 0, off_Blp = 0, off_R = 0, off_cs = 0, off_red = 0;
+  // byte input
+  size_t off_ub0 = 0, off_ub1 = 0, off_ubp = 0, off_x64 = 0, off_sl = 0, off_ex = 0;
   // adjoint (GLS_KEEP_FOR_GRAD)
   size_t off_Phi = 0, off_Lbar = 0, off_T1 = 0, off_T2 = 0, off_Xtb = 0, off_Xb = 0;
   size_t off_Cb = 0, off_eb = 0, off_ct = 0, off_Wb = 0, off_W0b = 0, off_acc = 0;
@@ -59,6 +61,12 @@ struct gls_ctx {
   double* R = nullptr;      // N x bcp FP64 refinement residuals
   double* cs = nullptr;     // bcp per-column scale factors
   double* red = nullptr;    // [0]: 2^-e of the factor; [8..]: reduction scratch
+  // byte input
+  uint8_t* ub[2] = {nullptr, nullptr};  // streaming staging, n x block_cols bytes
+  uint8_t* ubp = nullptr;   // N x bcp packed bytes (GLS_INT8_EMU operand)
+  double* x64 = nullptr;    // N x block_cols bytes widened to FP64 (other precisions)
+  int8_t* sl = nullptr;     // OZ_SLICES x N x N int8 slices of L^-1 (GLS_INT8_EMU)
+  int* ex = nullptr;        // N row exponents of L^-1 (GLS_INT8_EMU)
   // adjoint state (GLS_KEEP_FOR_GRAD)
   bool grad = false;
   double* Phi = nullptr;    // N x N, lower triangle of Phi (zero padding)
@@ -118,5 +126,7 @@ void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, 
                       hipStream_t s);
 gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double* b, int64_t ld_b, double* s2,
                          double* v, int* st, hipStream_t s);
+gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, double* b, int64_t ld_b, double* s2,
+                            double* v, int* st, hipStream_t s);
 
 }  // namespace gls

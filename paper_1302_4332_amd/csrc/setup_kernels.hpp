@@ -61,66 +61,105 @@ __global__ void pack_covariates_kernel(double* __restrict__ Wp, int N, int n, in
   }
 }
 
+// 1/p to full double precision: hardware reciprocal estimate plus two
+// Newton steps (off the IEEE division's long sequence; used where the last
+// bit is immaterial, the pivots of the right-looking update).
+__device__ __forceinline__ double fast_rcp(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  double e = __builtin_fma(-p, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-p, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // One diagonal block of the blocked factorization, entirely on chip:
-//   Cholesky of the NB_LEAF x NB_LEAF lower block at A (ld), right-looking with
-//   one barrier per column (the trailing update uses the unscaled column and
-//   the pivot, so column j is never rewritten in its own step), then the
-//   inverse of the factor by forward substitution with one lane per column
-//   and the column held in registers.  Writes the factor (zero upper part)
-//   back to A and the inverse (zero upper part) to Ainv (ld).  A non-positive
-//   or NaN pivot sets *info = row0 + j + 1 if *info is still 0 (the 1-based
-//   global pivot; blocks run in order, so the first failure wins).
+//   Cholesky of the NB_LEAF x NB_LEAF lower block at A (ld), right-looking.
+//   Each thread keeps its share of the trailing matrix in registers (column
+//   kc = t % 64, rows kc + t/64 + 4q, q < 16; entries past the block are
+//   dummies, so no per-entry branches).  At step j the owners of column j
+//   publish it (unscaled) into its own LDS column, one barrier per step, and
+//   every later column is updated with that column times 1/pivot.  The
+//   columns are scaled by 1/sqrt(pivot) after the loop, in parallel.
+//   Then the inverse of the factor, right-looking as well: lane jj holds
+//   column jj of the inverse in registers; at step k its entry k is scaled by
+//   1/L[k][k] and subtracted, times L[i][k], from every later entry i (the
+//   same terms, in the same order, as forward substitution).
+//   Writes the factor (zero upper part) back to A and the inverse (zero upper
+//   part) to Ainv (ld).  A non-positive or NaN pivot sets *info = row0 + j + 1
+//   if *info is still 0 (the 1-based global pivot; blocks run in order, so the
+//   first failure wins).
 __global__ __launch_bounds__(256) void leaf_potrf_trtri_kernel(double* __restrict__ A, double* __restrict__ Ainv,
                                                                int64_t ld, int row0, int* __restrict__ info) {
   constexpr int B = NB_LEAF;
+  constexpr int SC = 2 * B;   // column stride of lt (room for the dummy rows)
   constexpr int S = B + 1;
+  constexpr int QR = B / 4;   // register rows per thread
   static_assert(B == 64, "one lane per column of the block");
-  __shared__ double a[B * S];   // working copy, a[i + k * S] = A[i][k]
-  __shared__ double l[B * S];   // factor, row-major: l[i * S + k] = L[i][k]
+  __shared__ double lt[B * SC];   // column j of the factor: lt[j * SC + i] = L[i][j]
+  __shared__ double rs[B];        // 1 / sqrt(pivot j) = 1 / L[j][j]
+  __shared__ double xo[B * S];    // inverse, column-major staging for the store
   const int t = threadIdx.x;
-  for (int idx = t; idx < B * B; idx += blockDim.x) {
-    const int i = idx % B, k = idx / B;
-    a[i + k * S] = (i >= k) ? A[(int64_t)i + (int64_t)k * ld] : 0.0;
-    l[i * S + k] = 0.0;
-  }
-  __syncthreads();
   const int kc = t & (B - 1);
   const int r0 = t >> 6;
-  bool failed = false;
+  double a[QR];
+#pragma unroll
+  for (int q = 0; q < QR; ++q) {
+    const int i = kc + r0 + 4 * q;
+    a[q] = (i < B) ? A[(int64_t)i + (int64_t)kc * ld] : 0.0;
+  }
   for (int j = 0; j < B; ++j) {
-    const double piv = a[j + j * S];
-    if (t == 0 && !failed && !(piv > 0.0)) {
-      failed = true;
-      if (*info == 0) *info = row0 + j + 1;
-    }
-    if (t < B && t >= j) {
-      const double d = sqrt(piv);
-      l[t * S + j] = (t == j) ? d : a[t + j * S] / d;
-    }
-    if (kc > j) {
-      const double lk = a[kc + j * S] / piv;
-      for (int i = kc + r0; i < B; i += 4) a[i + kc * S] -= a[i + j * S] * lk;
+    double* cj = lt + j * SC;
+    if (kc == j) {
+#pragma unroll
+      for (int q = 0; q < QR; ++q) cj[kc + r0 + 4 * q] = a[q];
     }
     __syncthreads();
+    const double lk = (kc > j) ? cj[kc] * fast_rcp(cj[j]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < QR; ++q) a[q] -= cj[kc + r0 + 4 * q] * lk;
   }
-  if (t < B) {
-    const int jj = t;
-    double x[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-      double s = (i == jj) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) s -= l[i * S + k] * x[k];
-      x[i] = (i >= jj) ? s / l[i * S + i] : 0.0;
+  if (t == 0) {
+    for (int j = 0; j < B; ++j) {
+      if (!(lt[j * SC + j] > 0.0)) {
+        if (*info == 0) *info = row0 + j + 1;
+        break;
+      }
     }
-#pragma unroll
-    for (int i = 0; i < B; ++i) a[i + jj * S] = x[i];
+  }
+  if (t < B) rs[t] = 1.0 / sqrt(lt[t * SC + t]);
+  __syncthreads();
+  for (int idx = t; idx < B * B; idx += blockDim.x) {
+    const int i = idx % B, j = idx / B;
+    if (i > j) lt[j * SC + i] *= rs[j];
+    else if (i == j) lt[j * SC + i] = sqrt(lt[j * SC + i]);
   }
   __syncthreads();
   for (int idx = t; idx < B * B; idx += blockDim.x) {
     const int i = idx % B, k = idx / B;
-    A[(int64_t)i + (int64_t)k * ld] = (i >= k) ? l[i * S + k] : 0.0;
-    Ainv[(int64_t)i + (int64_t)k * ld] = a[i + k * S];
+    A[(int64_t)i + (int64_t)k * ld] = (i >= k) ? lt[k * SC + i] : 0.0;
+  }
+  if (t < B) {
+    // Sliding window: before step k, w[d] holds entry k + d of the lane's
+    // column (entries past the block are dummies, never stored).  A runtime
+    // loop over k keeps the code small: straight-line code run once would be
+    // bound by instruction fetch.
+    const int jj = t;
+    double w[B];
+#pragma unroll
+    for (int d = 0; d < B; ++d) w[d] = (d == jj) ? 1.0 : 0.0;
+    for (int k = 0; k < B; ++k) {
+      const double xk = w[0] * rs[k];
+      xo[k + jj * S] = xk;
+      const double* lk = lt + k * SC + k;   // L[k + d][k] for d >= 1 (rows past the block: dummies)
+#pragma unroll
+      for (int d = 1; d < B; ++d) w[d - 1] = w[d] - lk[d] * xk;
+      w[B - 1] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < B * B; idx += blockDim.x) {
+    const int i = idx % B, k = idx / B;
+    Ainv[(int64_t)i + (int64_t)k * ld] = xo[i + k * S];
   }
 }
 

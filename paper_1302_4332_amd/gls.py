@@ -19,9 +19,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgls.so")
 
-GLS_FP64, GLS_FP32_IR, GLS_FP16_IR, GLS_BF16_IR = 0, 1, 2, 3
-PRECISIONS = {"fp64": GLS_FP64, "fp32_ir": GLS_FP32_IR, "fp16_ir": GLS_FP16_IR, "bf16_ir": GLS_BF16_IR}
+GLS_FP64, GLS_FP32_IR, GLS_FP16_IR, GLS_BF16_IR, GLS_INT8_EMU = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": GLS_FP64, "fp32_ir": GLS_FP32_IR, "fp16_ir": GLS_FP16_IR, "bf16_ir": GLS_BF16_IR,
+              "int8_emu": GLS_INT8_EMU}
 GLS_KEEP_FOR_GRAD = 1
+GLS_STREAM_SERIAL = 2
 
 STATUS = {0: "GLS_OK", -1: "GLS_ERR_ARG", -2: "GLS_ERR_NOT_SPD", -3: "GLS_ERR_HIP",
           -4: "GLS_ERR_WORKSPACE", -5: "GLS_ERR_STATE", -6: "GLS_ERR_RANK"}
@@ -64,6 +66,9 @@ SIGNATURES = {
     "gls_block": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _P, _P, _P]),
     "gls_stream": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
                                   ctypes.POINTER(GlsStreamStats)]),
+    "gls_block_u8": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _P, _P, _P]),
+    "gls_stream_u8": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
+                                     ctypes.POINTER(GlsStreamStats)]),
     "gls_backward_block": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
     "gls_backward_finish": (ctypes.c_int, [_P, _P, _P, _P]),
     "gls_profile_enable": (ctypes.c_int, [_P, _I32]),
@@ -114,9 +119,11 @@ def _need(t: torch.Tensor, name: str, dtype=torch.float64, cuda=True):
         raise ValueError(f"{name} must be contiguous")
 
 
-def make_opts(block_cols: int, precision="fp64", refine_sweeps: int = 0, keep_for_grad: bool = False) -> GlsOpts:
+def make_opts(block_cols: int, precision="fp64", refine_sweeps: int = 0, keep_for_grad: bool = False,
+              serial_stream: bool = False) -> GlsOpts:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return GlsOpts(prec, int(refine_sweeps), int(block_cols), GLS_KEEP_FOR_GRAD if keep_for_grad else 0)
+    flags = (GLS_KEEP_FOR_GRAD if keep_for_grad else 0) | (GLS_STREAM_SERIAL if serial_stream else 0)
+    return GlsOpts(prec, int(refine_sweeps), int(block_cols), flags)
 
 
 def workspace_bytes(n: int, p: int, opts: GlsOpts) -> int:
@@ -130,7 +137,7 @@ class GLSContext:
     """
 
     def __init__(self, Phi, h2, XL, y, *, block_cols: int, precision="fp64", refine_sweeps: int = 0,
-                 keep_for_grad: bool = False, stream=None):
+                 keep_for_grad: bool = False, serial_stream: bool = False, stream=None):
         _need(Phi, "Phi")
         _need(y, "y")
         n = Phi.shape[0]
@@ -139,7 +146,7 @@ class GLSContext:
         p = XL.shape[1] + 1
         XLc = XL.t().contiguous() if XL.shape[1] else None
         self.n, self.p = n, p
-        self.opts = make_opts(block_cols, precision, refine_sweeps, keep_for_grad)
+        self.opts = make_opts(block_cols, precision, refine_sweeps, keep_for_grad, serial_stream)
         nbytes = workspace_bytes(n, p, self.opts)
         if nbytes == 0:
             raise GLSError(-1, f"invalid sizes or options (n={n}, p={p}, block_cols={block_cols})")
@@ -188,6 +195,30 @@ class GLSContext:
                              _ptr(b), self.p, _ptr(sigma2), _ptr(v), _ptr(status), _stream(stream))
         _check(st)
 
+    def block_u8_into(self, G, b, sigma2, v, status, stream=None):
+        """One block of genotype bytes (mb, n) uint8 CUDA into caller-provided outputs."""
+        _need(G, "G", torch.uint8)
+        mb = G.shape[0]
+        if G.dim() != 2 or G.shape[1] != self.n:
+            raise ValueError(f"G must have shape (mb, {self.n})")
+        for t, name, dt in ((b, "b", torch.float64), (sigma2, "sigma2", torch.float64),
+                            (v, "v", torch.float64), (status, "status", torch.int32)):
+            _need(t, name, dt)
+            if t.shape[0] != mb or (name == "b" and tuple(t.shape) != (mb, self.p)):
+                raise ValueError(f"{name} has the wrong shape {tuple(t.shape)}")
+        _check(lib().gls_block_u8(self.handle, mb, _ptr(G), self.n, _ptr(b), self.p, _ptr(sigma2), _ptr(v),
+                                  _ptr(status), _stream(stream)))
+
+    def block_u8(self, G, stream=None):
+        mb = G.shape[0]
+        dev = G.device
+        b = torch.empty((mb, self.p), dtype=torch.float64, device=dev)
+        s2 = torch.empty(mb, dtype=torch.float64, device=dev)
+        v = torch.empty(mb, dtype=torch.float64, device=dev)
+        status = torch.empty(mb, dtype=torch.int32, device=dev)
+        self.block_u8_into(G, b, s2, v, status, stream)
+        return b, s2, v, status
+
     def block(self, XR, stream=None):
         """XR: (mb, n) float64 CUDA.  Returns b (mb, p), sigma2, v, status."""
         mb = XR.shape[0]
@@ -200,11 +231,14 @@ class GLSContext:
         return b, s2, v, status
 
     def stream(self, XR_host, col0: int = 0, out=None, compute_stream=None, copy_stream=None):
-        """Stream SNPs [col0, m) of a pinned host tensor XR_host (m, n).
+        """Stream SNPs [col0, m) of a pinned host tensor XR_host (m, n), float64
+        or uint8 genotype bytes.
 
         Returns (b, sigma2, v, status) host tensors and the stats struct.
         """
-        _need(XR_host, "XR_host", cuda=False)
+        _need(XR_host, "XR_host", XR_host.dtype if XR_host.dtype in (torch.uint8, torch.float64) else torch.float64,
+              cuda=False)
+        entry = lib().gls_stream_u8 if XR_host.dtype == torch.uint8 else lib().gls_stream
         m = XR_host.shape[0]
         if out is None:
             out = (torch.full((m, self.p), float("nan"), dtype=torch.float64).pin_memory(),
@@ -220,9 +254,9 @@ class GLSContext:
         stats = GlsStreamStats()
         cs = compute_stream or torch.cuda.current_stream()
         xs = copy_stream or torch.cuda.Stream()
-        st = lib().gls_stream(self.handle, m, col0, _ptr(XR_host), self.n, _ptr(b), _ptr(s2), _ptr(v),
-                              _ptr(status), ctypes.c_void_p(cs.cuda_stream), ctypes.c_void_p(xs.cuda_stream),
-                              ctypes.byref(stats))
+        st = entry(self.handle, m, col0, _ptr(XR_host), self.n, _ptr(b), _ptr(s2), _ptr(v),
+                   _ptr(status), ctypes.c_void_p(cs.cuda_stream), ctypes.c_void_p(xs.cuda_stream),
+                   ctypes.byref(stats))
         _check(st)
         return (b, s2, v, status), stats
 

@@ -102,6 +102,8 @@ def covariates(n: int, p: int, seed: int, kind: str = "sex_age") -> np.ndarray:
     """X_L, n x (p-1), column-major (Fortran order)."""
     rng = np.random.default_rng([seed, STREAM_XL])
     XL = np.empty((n, p - 1), dtype=np.float64, order="F")
+    if p == 1:
+        return XL
     XL[:, 0] = 1.0
     if kind == "sex_age":
         if p != 4:

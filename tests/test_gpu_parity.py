@@ -150,3 +150,15 @@ def test_stream_matches_block_and_resumes():
     assert (b2.numpy()[:700] == -7.0).all()
     assert np.array_equal(b2.numpy()[700:], ref["b"][700:])
     assert np.array_equal(st2.numpy()[700:], ref["status"][700:])
+
+
+def test_serial_stream_equals_overlapped():
+    """The no-overlap ablation gives bitwise the same results as the double-buffered stream."""
+    Phi, h2, XL, y, XR = _problem(330, 4, 700, seed=23)
+    host = torch.tensor(XR).pin_memory()
+    a = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=128)
+    b = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=128, serial_stream=True)
+    (ra, _, _, sa), _ = a.stream(host)
+    (rb, _, _, sb), stats = b.stream(host)
+    assert stats.blocks == 6 and stats.h2d_bytes == 8 * 330 * 700
+    assert np.array_equal(ra.numpy(), rb.numpy()) and np.array_equal(sa.numpy(), sb.numpy())
