@@ -132,6 +132,88 @@ def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
     return res
 
 
+def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
+    """Genotype bytes: the int8-slice product (FP64-accurate) with the SNP
+    matrix resident in HBM, and the streamed rates from pinned host memory
+    and from a file (1 byte per sample instead of 8)."""
+    import tempfile
+
+    import torch
+
+    from paper_1302_4332_amd.gls import GLSContext
+
+    w = st.w
+    n, p, bc, h2 = w.n, w.p, w.block_cols, w.h2
+    res = {}
+    G_d = X_d.to(torch.uint8)
+    b_d = torch.empty((m, p), dtype=torch.float64, device=dev)
+    s2_d = torch.empty(m, dtype=torch.float64, device=dev)
+    v_d = torch.empty(m, dtype=torch.float64, device=dev)
+    st_d = torch.empty(m, dtype=torch.int32, device=dev)
+
+    def study(profile):
+        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision="int8_emu")
+        if profile:
+            ctx.profile(True)
+        for j0 in range(0, m, bc):
+            j1 = min(m, j0 + bc)
+            ctx.block_u8_into(G_d[j0:j1], b_d[j0:j1], s2_d[j0:j1], v_d[j0:j1], st_d[j0:j1])
+        ph = ctx.profile_read() if profile else None
+        ctx.close()
+        return ph
+
+    study(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ph = study(True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    g = b_d.cpu().numpy()
+    ref = b_fp64_host.numpy()
+    ok = np.isfinite(ref).all(axis=1)
+    rel = np.max(np.abs(g[ok] - ref[ok]), axis=1) / np.max(np.abs(ref[ok]), axis=1)
+    wl, wms = ph["whiten"]
+    res["int8_emu_hbm"] = {
+        "snps_per_s": m / (ms / 1e3), "ms_per_study": ms, "slices": 8,
+        "product_ms": wms, "product_fp64_equiv_tflops": float(n) * n * m / (wms / 1e3) / 1e12,
+        "int8_tops": 8.0 * n * n * m / (wms / 1e3) / 1e12, "int8_peak_tops": 5000.0,
+        "max_rel_diff_vs_fp64_path": float(rel.max()),
+        "note": "same study, SNPs as bytes; product from exact int8 slice products (FP64-level accuracy)"}
+    log(f"int8 emulation: {m / (ms / 1e3):,.0f} SNPs/s, product {wms:.1f} ms, max rel diff vs FP64 path {rel.max():.2e}")
+    del b_d, s2_d, v_d, st_d
+    G_h = torch.empty((m, n), dtype=torch.uint8).pin_memory()
+    G_h.copy_(G_d)
+    del G_d
+    for prec in ("fp64", "int8_emu"):
+        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec)
+        ctx.stream(G_h)
+        (_, _, _, _), ss = ctx.stream(G_h)
+        res[f"stream_u8_{prec}"] = {"snps_per_s": m / (ss.wall_ms / 1e3), "wall_ms": ss.wall_ms,
+                                    "compute_ms": ss.compute_ms, "h2d_GBps": ss.h2d_bytes / (ss.wall_ms / 1e3) / 1e9}
+        log(f"stream bytes {prec}: {m / (ss.wall_ms / 1e3):,.0f} SNPs/s")
+        ctx.close()
+    # from storage: the byte matrix written to a file, then streamed through
+    # the reader thread and three host buffers; page cache dropped for the file
+    with tempfile.TemporaryDirectory(dir=os.environ.get("TMPDIR", "/tmp")) as d:
+        path = os.path.join(d, "snps.u8")
+        G_h.numpy().tofile(path)
+        for prec in ("fp64", "int8_emu"):
+            ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec)
+            fd = os.open(path, os.O_RDONLY)
+            os.fsync(fd) if hasattr(os, "fsync") else None
+            os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+            os.close(fd)
+            (_, _, _, _), fs = ctx.stream_file(path, m, torch.uint8)
+            res[f"stream_file_u8_{prec}"] = {"snps_per_s": m / (fs.wall_ms / 1e3), "wall_ms": fs.wall_ms,
+                                             "read_ms": fs.read_ms, "file_GBps": fs.file_bytes / (fs.read_ms / 1e3) / 1e9
+                                             if fs.read_ms else None, "compute_ms": fs.compute_ms,
+                                             "note": "page cache of the file dropped before the run"}
+            log(f"stream file bytes {prec}: {m / (fs.wall_ms / 1e3):,.0f} SNPs/s (read {fs.read_ms:.0f} ms)")
+            ctx.close()
+    del G_h
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +348,8 @@ def main():
 
     if not args.no_forms:
         out["forms"] = measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev)
+    if not args.no_forms:
+        out["bytes"] = measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_h)
     if not args.no_stream:
         host = torch.empty((m, n), dtype=torch.float64).pin_memory()
         host.copy_(X_d)

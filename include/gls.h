@@ -134,6 +134,8 @@ typedef struct {
   int64_t d2h_bytes;     /* device-to-host bytes                              */
   double wall_ms;        /* first copy enqueue to last result landed          */
   double compute_ms;     /* sum over blocks of the block's device time        */
+  int64_t file_bytes;    /* bytes read from storage (gls_stream_file)         */
+  double read_ms;        /* time the reader spent in read calls (gls_stream_file) */
 } gls_stream_stats;
 
 /* Streamed study (Sec. 3.1, the GPU half of the double/triple buffering):
@@ -158,6 +160,25 @@ gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0,
                          double* b_host, double* sigma2_host, double* v_host,
                          int32_t* status_host, void* compute_stream, void* copy_stream,
                          gls_stream_stats* stats_out);
+
+/* Streamed study read from storage (Sec. 3.1, both buffering levels): the
+ * SNP matrix is a file holding SNP j's n samples contiguously at byte
+ * offset + j * n * elem_bytes, as FP64 (elem_bytes 8) or genotype bytes
+ * (elem_bytes 1).  A reader thread reads block b+2 into one of three
+ * page-locked host buffers while block b+1 waits in another and block b is
+ * copied to the device (two device buffers alternate as in gls_stream); a
+ * host buffer is reused only once its copy has completed.  host_ws is the
+ * caller's page-locked host memory of gls_stream_file_host_bytes() bytes.
+ * Outputs, col0 and return as gls_stream; read errors give GLS_ERR_ARG
+ * (unopenable file) or GLS_ERR_STATE (short read), with gls_last_error().
+ * With GLS_STREAM_SERIAL the calling thread reads, copies and solves one
+ * block after another (no overlap at either level). */
+size_t gls_stream_file_host_bytes(gls_handle h, int32_t elem_bytes);
+gls_status gls_stream_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bytes,
+                           int64_t m, int64_t col0, void* host_ws, size_t host_ws_bytes,
+                           double* b_host, double* sigma2_host, double* v_host,
+                           int32_t* status_host, void* compute_stream, void* copy_stream,
+                           gls_stream_stats* stats_out);
 
 /* Adjoint of one SNP block (requires GLS_KEEP_FOR_GRAD at setup).
  * Given cotangents b_bar (p x mb, ld p), sigma2_bar (mb), v_bar (mb) of the

@@ -45,6 +45,8 @@ gls_status arg_fail(const char* what) {
   return GLS_ERR_ARG;
 }
 
+void set_last_error_str(const char* what) { set_err("%s", what); }
+
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int64_t padded_n(int64_t n) { return (n + NPAD - 1) / NPAD * NPAD; }

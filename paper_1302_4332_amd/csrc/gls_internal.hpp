@@ -116,6 +116,7 @@ class PhaseTimer {
 
 gls_status hip_fail(hipError_t e, const char* what);
 gls_status arg_fail(const char* what);
+void set_last_error_str(const char* what);
 int64_t padded_n(int64_t n);
 bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl);
 

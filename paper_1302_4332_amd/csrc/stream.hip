@@ -8,8 +8,15 @@
 // triangular product, and only b, sigma2, v and status go back.
 #include <hip/hip_runtime.h>
 
+#include <fcntl.h>
+#include <unistd.h>
+
+#include <cerrno>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "gls_internal.hpp"
@@ -162,4 +169,230 @@ extern "C" gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0, const
                                     void* compute_stream, void* copy_stream, gls_stream_stats* stats_out) {
   return stream_impl(h, m, col0, G_host, ld_g, b_host, sigma2_host, v_host, status_host, compute_stream,
                      copy_stream, stats_out);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming from storage: reader thread -> three host buffers -> two device
+// buffers.
+
+namespace {
+
+struct FileRing {
+  std::mutex mu;
+  std::condition_variable cv;
+  int64_t filled[3] = {-1, -1, -1};  // block held by each host buffer (-1: none)
+  bool free_[3] = {true, true, true};
+  bool stop = false;
+  int err = 0;                        // errno of a failed read, or -1 for a short read
+  double read_ms = 0.0;
+  int64_t bytes = 0;
+};
+
+bool read_fully(int fd, void* dst, size_t len, off_t off, int* err) {
+  char* p = static_cast<char*>(dst);
+  while (len > 0) {
+    ssize_t r = pread(fd, p, len, off);
+    if (r < 0) {
+      if (errno == EINTR) continue;
+      *err = errno;
+      return false;
+    }
+    if (r == 0) {
+      *err = -1;
+      return false;
+    }
+    p += r;
+    off += r;
+    len -= (size_t)r;
+  }
+  return true;
+}
+
+size_t host_ring_bytes(const Ctx* c, int elem) {
+  const size_t one = (size_t)c->n * (size_t)c->bc * (size_t)elem;
+  return 3 * ((one + 4095) / 4096 * 4096);
+}
+
+template <typename T>
+gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t col0, char* host,
+                            double* b_host, double* sigma2_host, double* v_host, int32_t* status_host,
+                            hipStream_t sc, hipStream_t sx_in, gls_stream_stats* stats_out) {
+  const int64_t n = c->n, bc = c->bc;
+  const int p = c->p;
+  const bool serial = (c->opts.flags & GLS_STREAM_SERIAL) != 0;
+  hipStream_t sx = serial ? sc : sx_in;
+  const int64_t nblk = (m - col0 + bc - 1) / bc;
+  gls_stream_stats st{};
+  if (nblk == 0) {
+    if (stats_out) *stats_out = st;
+    return GLS_OK;
+  }
+  const size_t slot_bytes = host_ring_bytes(c, sizeof(T)) / 3;
+  T* hb[3];
+  for (int i = 0; i < 3; ++i) hb[i] = reinterpret_cast<T*>(host + i * slot_bytes);
+  auto cols_of = [&](int64_t blk) { return std::min<int64_t>(bc, m - col0 - blk * bc); };
+  auto file_off = [&](int64_t blk) { return (off_t)(offset + (col0 + blk * bc) * n * (int64_t)sizeof(T)); };
+
+  EventPool pool;
+  hipError_t e;
+  // per block: compute start/stop, H2D done; plus wall start/stop
+  if ((e = pool.make(3 * nblk + 2)) != hipSuccess) return hip_fail(e, "gls_stream_file: event create");
+  hipEvent_t wall0 = pool.ev[3 * nblk], wall1 = pool.ev[3 * nblk + 1];
+  auto ev_h2d = [&](int64_t blk) { return pool.ev[2 * nblk + blk]; };
+
+  FileRing ring;
+  std::thread reader;
+  if (!serial) {
+    reader = std::thread([&] {
+      for (int64_t blk = 0; blk < nblk; ++blk) {
+        const int slot = (int)(blk % 3);
+        {
+          std::unique_lock<std::mutex> lk(ring.mu);
+          ring.cv.wait(lk, [&] { return ring.free_[slot] || ring.stop; });
+          if (ring.stop) return;
+          ring.free_[slot] = false;
+        }
+        const size_t len = (size_t)(cols_of(blk) * n) * sizeof(T);
+        int err = 0;
+        auto t0 = std::chrono::steady_clock::now();
+        const bool ok = read_fully(fd, hb[slot], len, file_off(blk), &err);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        std::lock_guard<std::mutex> lk(ring.mu);
+        ring.read_ms += ms;
+        if (!ok) {
+          ring.err = err;
+          ring.cv.notify_all();
+          return;
+        }
+        ring.bytes += (int64_t)len;
+        ring.filled[slot] = blk;
+        ring.cv.notify_all();
+      }
+    });
+  }
+  auto finish_reader = [&] {
+    if (reader.joinable()) {
+      {
+        std::lock_guard<std::mutex> lk(ring.mu);
+        ring.stop = true;
+      }
+      ring.cv.notify_all();
+      reader.join();
+    }
+  };
+  auto fail = [&](gls_status s) {
+    finish_reader();
+    (void)hipStreamSynchronize(sc);
+    (void)hipStreamSynchronize(sx);
+    return s;
+  };
+
+  if ((e = hipEventRecord(wall0, sx)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    const int slot = (int)(blk % 3), cur = (int)(blk & 1);
+    const int64_t cols = cols_of(blk);
+    const int64_t col = col0 + blk * bc;
+    if (serial) {
+      int err = 0;
+      auto t0 = std::chrono::steady_clock::now();
+      const size_t len = (size_t)(cols * n) * sizeof(T);
+      if (!read_fully(fd, hb[slot], len, file_off(blk), &err)) {
+        set_last_error_str(err > 0 ? "gls_stream_file: read failed" : "gls_stream_file: file shorter than m columns");
+        return fail(GLS_ERR_STATE);
+      }
+      ring.read_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      ring.bytes += (int64_t)len;
+    } else {
+      std::unique_lock<std::mutex> lk(ring.mu);
+      ring.cv.wait(lk, [&] { return ring.filled[slot] == blk || ring.err != 0; });
+      if (ring.err != 0 && ring.filled[slot] != blk) {
+        const int err = ring.err;
+        lk.unlock();
+        set_last_error_str(err > 0 ? "gls_stream_file: read failed" : "gls_stream_file: file shorter than m columns");
+        return fail(GLS_ERR_STATE);
+      }
+    }
+    // device buffer cur may be overwritten once the solve two blocks back is done
+    if (!serial && blk >= 2 && (e = hipStreamWaitEvent(sx, c->ev_comp[cur], 0)) != hipSuccess)
+      return fail(hip_fail(e, "gls_stream_file: wait"));
+    if ((e = h2d_block(stage(c, cur, (const T*)nullptr), n, hb[slot], n, cols, sx)) != hipSuccess)
+      return fail(hip_fail(e, "gls_stream_file: H2D"));
+    if ((e = hipEventRecord(ev_h2d(blk), sx)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
+    st.h2d_bytes += (int64_t)sizeof(T) * n * cols;
+    if ((e = hipStreamWaitEvent(sc, ev_h2d(blk), 0)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: wait"));
+    if ((e = hipEventRecord(pool.ev[2 * blk], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
+    gls_status r = solve_block(c, (int)cols, stage(c, cur, (const T*)nullptr), n, c->ob, p, c->os2, c->ov, c->ost, sc);
+    if (r != GLS_OK) return fail(r);
+    if ((e = hipEventRecord(c->ev_comp[cur], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
+    if ((e = hipEventRecord(pool.ev[2 * blk + 1], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
+    if ((e = hipMemcpyAsync(b_host + col * p, c->ob, sizeof(double) * p * cols, hipMemcpyDeviceToHost, sc)) ||
+        (e = hipMemcpyAsync(sigma2_host + col, c->os2, sizeof(double) * cols, hipMemcpyDeviceToHost, sc)) ||
+        (e = hipMemcpyAsync(v_host + col, c->ov, sizeof(double) * cols, hipMemcpyDeviceToHost, sc)) ||
+        (e = hipMemcpyAsync(status_host + col, c->ost, sizeof(int32_t) * cols, hipMemcpyDeviceToHost, sc)))
+      return fail(hip_fail(e, "gls_stream_file: D2H"));
+    st.d2h_bytes += (int64_t)(sizeof(double) * (p + 2) + sizeof(int32_t)) * cols;
+    if (serial) {
+      if ((e = hipStreamSynchronize(sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: synchronize"));
+    } else if (blk >= 1) {
+      // the previous block's host buffer is free once its copy has landed
+      if ((e = hipEventSynchronize(ev_h2d(blk - 1))) != hipSuccess)
+        return fail(hip_fail(e, "gls_stream_file: synchronize"));
+      std::lock_guard<std::mutex> lk(ring.mu);
+      ring.free_[(blk - 1) % 3] = true;
+      ring.filled[(blk - 1) % 3] = -1;
+      ring.cv.notify_all();
+    }
+  }
+  if ((e = hipEventRecord(wall1, sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
+  if ((e = hipStreamSynchronize(sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: synchronize"));
+  if ((e = hipStreamSynchronize(sx)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: synchronize"));
+  finish_reader();
+  float ms = 0.f;
+  if ((e = hipEventElapsedTime(&ms, wall0, wall1)) != hipSuccess) return hip_fail(e, "gls_stream_file: elapsed");
+  st.wall_ms = ms;
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    float t = 0.f;
+    if ((e = hipEventElapsedTime(&t, pool.ev[2 * blk], pool.ev[2 * blk + 1])) != hipSuccess)
+      return hip_fail(e, "gls_stream_file: elapsed");
+    st.compute_ms += t;
+  }
+  st.blocks = nblk;
+  st.file_bytes = ring.bytes;
+  st.read_ms = ring.read_ms;
+  if (stats_out) *stats_out = st;
+  return GLS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t gls_stream_file_host_bytes(gls_handle h, int32_t elem_bytes) {
+  const Ctx* c = h;
+  if (!c || !c->ready || (elem_bytes != 8 && elem_bytes != 1)) return 0;
+  return host_ring_bytes(c, elem_bytes);
+}
+
+extern "C" gls_status gls_stream_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bytes, int64_t m,
+                                      int64_t col0, void* host_ws, size_t host_ws_bytes, double* b_host,
+                                      double* sigma2_host, double* v_host, int32_t* status_host,
+                                      void* compute_stream, void* copy_stream, gls_stream_stats* stats_out) {
+  Ctx* c = h;
+  if (!c || !c->ready) return arg_fail("gls_stream_file: handle is not set up"), GLS_ERR_STATE;
+  if (!path || offset < 0 || m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream_file: bad path/offset/m/col0");
+  if (elem_bytes != 8 && elem_bytes != 1) return arg_fail("gls_stream_file: elem_bytes must be 8 or 1");
+  if (!host_ws || host_ws_bytes < host_ring_bytes(c, elem_bytes))
+    return arg_fail("gls_stream_file: host_ws smaller than gls_stream_file_host_bytes()");
+  if (!b_host || !sigma2_host || !v_host || !status_host) return arg_fail("gls_stream_file: NULL host output");
+  const int fd = open(path, O_RDONLY);
+  if (fd < 0) return arg_fail("gls_stream_file: cannot open the file");
+  gls_status st;
+  if (elem_bytes == 8)
+    st = stream_file_impl<double>(c, fd, offset, m, col0, static_cast<char*>(host_ws), b_host, sigma2_host, v_host,
+                                  status_host, static_cast<hipStream_t>(compute_stream),
+                                  static_cast<hipStream_t>(copy_stream), stats_out);
+  else
+    st = stream_file_impl<uint8_t>(c, fd, offset, m, col0, static_cast<char*>(host_ws), b_host, sigma2_host, v_host,
+                                   status_host, static_cast<hipStream_t>(compute_stream),
+                                   static_cast<hipStream_t>(copy_stream), stats_out);
+  close(fd);
+  return st;
 }

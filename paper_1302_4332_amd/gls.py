@@ -36,7 +36,8 @@ class GlsOpts(ctypes.Structure):
 
 class GlsStreamStats(ctypes.Structure):
     _fields_ = [("blocks", ctypes.c_int64), ("h2d_bytes", ctypes.c_int64), ("d2h_bytes", ctypes.c_int64),
-                ("wall_ms", ctypes.c_double), ("compute_ms", ctypes.c_double)]
+                ("wall_ms", ctypes.c_double), ("compute_ms", ctypes.c_double), ("file_bytes", ctypes.c_int64),
+                ("read_ms", ctypes.c_double)]
 
 
 class GlsPhaseStats(ctypes.Structure):
@@ -69,6 +70,9 @@ SIGNATURES = {
     "gls_block_u8": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _P, _P, _P]),
     "gls_stream_u8": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
                                      ctypes.POINTER(GlsStreamStats)]),
+    "gls_stream_file_host_bytes": (ctypes.c_size_t, [_P, _I32]),
+    "gls_stream_file": (ctypes.c_int, [_P, ctypes.c_char_p, _I64, _I32, _I64, _I64, _P, ctypes.c_size_t,
+                                       _P, _P, _P, _P, _P, _P, ctypes.POINTER(GlsStreamStats)]),
     "gls_backward_block": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
     "gls_backward_finish": (ctypes.c_int, [_P, _P, _P, _P]),
     "gls_profile_enable": (ctypes.c_int, [_P, _I32]),
@@ -229,6 +233,28 @@ class GLSContext:
         status = torch.empty(mb, dtype=torch.int32, device=dev)
         self.block_into(XR, b, s2, v, status, stream)
         return b, s2, v, status
+
+    def stream_file(self, path: str, m: int, dtype=torch.float64, offset: int = 0, col0: int = 0, out=None,
+                    host_ws=None, compute_stream=None, copy_stream=None):
+        """Stream SNPs [col0, m) from a file (SNP-major, float64 or uint8 genotype bytes)."""
+        elem = 8 if dtype == torch.float64 else 1
+        need = int(lib().gls_stream_file_host_bytes(self.handle, elem))
+        if host_ws is None or host_ws.numel() < need:
+            host_ws = torch.empty(need, dtype=torch.uint8).pin_memory()
+        if out is None:
+            out = (torch.full((m, self.p), float("nan"), dtype=torch.float64).pin_memory(),
+                   torch.full((m,), float("nan"), dtype=torch.float64).pin_memory(),
+                   torch.full((m,), float("nan"), dtype=torch.float64).pin_memory(),
+                   torch.full((m,), -1, dtype=torch.int32).pin_memory())
+        b, s2, v, status = out
+        stats = GlsStreamStats()
+        cs = compute_stream or torch.cuda.current_stream()
+        xs = copy_stream or torch.cuda.Stream()
+        st = lib().gls_stream_file(self.handle, path.encode(), offset, elem, m, col0, _ptr(host_ws), host_ws.numel(),
+                                   _ptr(b), _ptr(s2), _ptr(v), _ptr(status), ctypes.c_void_p(cs.cuda_stream),
+                                   ctypes.c_void_p(xs.cuda_stream), ctypes.byref(stats))
+        _check(st)
+        return (b, s2, v, status), stats
 
     def stream(self, XR_host, col0: int = 0, out=None, compute_stream=None, copy_stream=None):
         """Stream SNPs [col0, m) of a pinned host tensor XR_host (m, n), float64
