@@ -61,6 +61,7 @@ struct GemmArgs {
   // map_gm x map_gn tiles per co-resident group on one XCD (0 = defaults)
   int map_desc;
   int map_gm, map_gn;
+  int map_slab;   // 1: column groups outer (a slab of GN column tiles meets every row tile in turn)
 };
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
@@ -94,8 +95,15 @@ struct XcdMap {
     int per_group = GM * GN;
     int g = s / per_group;
     int w = s - g * per_group;
-    int rgi = g / cg;                 // row group (heavy first)
-    int cgi = g - rgi * cg;           // column group
+    const int rg = (R + GM - 1) / GM;
+    int rgi, cgi;
+    if (ga.map_slab) {                // column group outer, row groups heavy first inside
+      cgi = g / rg;
+      rgi = g - cgi * rg;
+    } else {                          // row group (heavy first) outer
+      rgi = g / cg;
+      cgi = g - rgi * cg;
+    }
     int kl = rgi * GM + (w % GM);     // local row index on this XCD
     int j = cgi * GN + (w / GM);
     if (kl >= R || j >= Nt) return false;
