@@ -118,7 +118,9 @@ gls_status gls_block(gls_handle h, int32_t mb, const double* XR, int64_t ld_xr,
                      int32_t* snp_status, void* stream);
 
 /* One SNP block given as genotype bytes: G is n x mb uint8 (ld_g >= n),
- * entries 0..127 (dosages 0, 1, 2).  Same outputs and asynchrony as
+ * entries 0..127 (dosages 0, 1, 2).  GLS_INT8_EMU sums exact int32 products,
+ * so it needs n * 127 * max(G) < 2^31: any byte value for n <= 133,000,
+ * dosages 0..2 for n up to 8.4 million.  Same outputs and asynchrony as
  * gls_block.  With GLS_FP64 or the mixed forms the bytes are widened to FP64
  * on the device and the results are bitwise those of gls_block on the same
  * values; with GLS_INT8_EMU the product runs on the integer matrix cores
