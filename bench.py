@@ -151,16 +151,15 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
     v_d = torch.empty(m, dtype=torch.float64, device=dev)
     st_d = torch.empty(m, dtype=torch.int32, device=dev)
 
+    ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision="int8_emu")
+
     def study(profile):
-        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision="int8_emu")
         if profile:
             ctx.profile(True)
         for j0 in range(0, m, bc):
             j1 = min(m, j0 + bc)
             ctx.block_u8_into(G_d[j0:j1], b_d[j0:j1], s2_d[j0:j1], v_d[j0:j1], st_d[j0:j1])
-        ph = ctx.profile_read() if profile else None
-        ctx.close()
-        return ph
+        return ctx.profile_read() if profile else None
 
     study(False)
     torch.cuda.synchronize()
@@ -168,6 +167,7 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
     ph = study(True)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
+    ctx.close()
     g = b_d.cpu().numpy()
     ref = b_fp64_host.numpy()
     ok = np.isfinite(ref).all(axis=1)

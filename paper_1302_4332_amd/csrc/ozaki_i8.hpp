@@ -94,16 +94,68 @@ struct OzArgs {
 
 // v_mfma_i32_16x16x64_i8 operand layout (checked on gfx950 with known
 // operands): lane l holds A[l % 16][16 (l / 16) + e] and B[16 (l / 16) + e][l % 16]
-// for bytes e = 0..15; accumulator element t is C[4 (l / 16) + t][l % 16].
+// for bytes e = 0..15 (any k order shared by A and B gives the same sum);
+// accumulator element t is D[4 (l / 16) + t][l % 16].
 //
-// 64 x 64 output tiles, k in slices of 64; four waves, each a 64 x 16 strip
-// (four 16x16 int32 accumulators per slice).  The byte block is staged once
-// per k-slice and shared by all S factor slices.
-__global__ __launch_bounds__(256) void ozaki_i8_kernel(OzArgs g) {
-  constexpr int BM = 64, BN = 64, BK = 64, S = OZ_SLICES;
-  constexpr int SK = BK + 16;   // LDS row stride in bytes (16-byte aligned, staggered)
-  __shared__ int8_t As[2][S][BM * SK];
-  __shared__ uint8_t Bs[2][BN * SK];
+// The kernel computes the transpose, D = X^T a_s^T, so that the accumulator's
+// fast index (l % 16) runs down a column of the column-major result and the
+// FP64 stores are 128-byte runs.  A workgroup of eight waves owns a 32 x 256
+// output tile; wave w takes the 16-row strip w & 1 and the 64-column strip
+// w >> 1, holding S x 4 accumulators (one per factor slice and 16-column
+// group).  Per 64-deep k step a wave reads four byte fragments and one
+// fragment per slice from LDS and issues 4 S MFMAs.
+//
+// Operands reach LDS by direct global-to-LDS loads (global_load_lds_dwordx4:
+// no staging registers) into a ring of OZ_STAGES buffers, OZ_STAGES - 1 steps
+// ahead of the MFMAs.  The loads are issued from inline assembly so that the
+// compiler does not drain them at every barrier; the kernel waits on vmcnt
+// itself.  One load instruction moves 1 KB: sixteen 64-byte rows, lane l
+// writing bytes [16 l, 16 l + 16) of it.  Chunk c of row r is stored in slot
+// c ^ oz_swz(r), so that a fragment read (sixteen rows, one chunk each) puts
+// every eight consecutive lanes on distinct 128-byte bank lines and all sixteen
+// on distinct 256-byte lines.
+constexpr int OZ_BM = 32, OZ_BN = 256, OZ_BK = 64, OZ_THREADS = 512, OZ_STAGES = 4;
+
+__device__ __forceinline__ int oz_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+__device__ __forceinline__ uint32_t oz_lds_address(const void* p) {
+  return (uint32_t)(uintptr_t)((const __attribute__((address_space(3))) char*)p);
+}
+
+// 16 bytes per lane from global memory to LDS at lds + 16 * lane (lds: wave-uniform).
+// M0 carries the LDS address; it is saved and restored around the load.
+__device__ __forceinline__ void oz_load_lds16(const void* src, uint32_t lds) {
+  uint32_t keep;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %2\n\t"
+      "global_load_lds_dwordx4 %1, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(keep)
+      : "v"(src), "s"(lds)
+      : "memory");
+}
+
+// wait until at most 4 n of this wave's global-to-LDS loads are in flight
+// (n whole stages: four load instructions each)
+__device__ __forceinline__ void oz_wait_stages(int n) {
+  switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+  }
+}
+
+__global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
+  constexpr int BM = OZ_BM, BN = OZ_BN, BK = OZ_BK, S = OZ_SLICES, NW = OZ_THREADS / 64, NS = OZ_STAGES;
+  constexpr int RB = BK;                         // bytes per LDS row
+  constexpr int ABYTES = S * BM * RB, STAGE = ABYTES + BN * RB;
+  constexpr int QA = S * BM / 16 / NW;           // 1 KB load instructions per wave and stage
+  constexpr int QB = BN / 16 / NW;
+  static_assert(BK == 64 && QA == 2 && QB == 2 && NS >= 2 && NS <= 5, "loader and wait counts assume this split");
+  static_assert(NS * STAGE <= 160 * 1024, "LDS");
+  __shared__ __align__(1024) int8_t smem[NS * STAGE];
 
   int ti, tj;
   {
@@ -116,59 +168,77 @@ __global__ __launch_bounds__(256) void ozaki_i8_kernel(OzArgs g) {
   }
   const int i0 = ti * BM, j0 = tj * BN;
   const int nk = (i0 + BM + BK - 1) / BK;   // lower triangular factor: k < i0 + BM
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave & 1, wj = wave >> 1;
   const int64_t plane = (int64_t)g.N * g.N;
+
+  // loader: instruction q of this wave fills rows 16 (q NW + wave) .. +15
+  const int lrow = lane >> 2, lchunk = ((lane & 3) ^ oz_swz(lrow)) * 16;
+  const int8_t* pa[QA];
+  const uint8_t* pb[QB];
+#pragma unroll
+  for (int q = 0; q < QA; ++q) {
+    const int r = 16 * (q * NW + wave) + lrow, s = r / BM, ri = r % BM;
+    pa[q] = g.A + s * plane + (int64_t)(i0 + ri) * g.N + lchunk;
+  }
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int j = min(j0 + 16 * (q * NW + wave) + lrow, g.ncols - 1);   // columns past the end: any valid
+    pb[q] = g.B + (int64_t)j * g.N + lchunk;                            // column, their results are dropped
+  }
+  const uint32_t lds0 = oz_lds_address(smem);
+  auto issue = [&](int kstep) {
+    const uint32_t base = lds0 + (uint32_t)((kstep % NS) * STAGE);
+    const int kt = kstep * BK;
+#pragma unroll
+    for (int q = 0; q < QA; ++q)
+      oz_load_lds16(pa[q] + kt, __builtin_amdgcn_readfirstlane(base + 1024 * (q * NW + wave)));
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+      oz_load_lds16(pb[q] + kt, __builtin_amdgcn_readfirstlane(base + ABYTES + 1024 * (q * NW + wave)));
+  };
 
   i4_t acc[S][4];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) acc[s][a] = i4_t{0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) acc[s][c] = i4_t{0, 0, 0, 0};
 
-  // loader: 16-byte chunks; a 64 x 64 byte tile is 256 chunks, one per thread
-  const int lr = tid / 4, lc = (tid % 4) * 16;
-  uint4 ra[S], rb;
-  auto load = [&](int kt) {
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-      ra[s] = *reinterpret_cast<const uint4*>(g.A + s * plane + (int64_t)(i0 + lr) * g.N + kt + lc);
-    rb = *reinterpret_cast<const uint4*>(g.B + (int64_t)(kt + lc) + (int64_t)(j0 + lr) * g.N);
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) *reinterpret_cast<uint4*>(&As[buf][s][lr * SK + lc]) = ra[s];
-    *reinterpret_cast<uint4*>(&Bs[buf][lr * SK + lc]) = rb;
-  };
-  load(0);
-  store(0);
-  __syncthreads();
+  // fragment offsets: row (wi 16 + fr) of each slice, row (wj 64 + 16 c + fr) of the bytes,
+  // chunk lane >> 4 in slot chunk ^ oz_swz(fr)
+  const int fr = lane & 15, slot = ((lane >> 4) ^ oz_swz(fr)) * 16;
+  const int oa = (wi * 16 + fr) * RB + slot;
+  const int ob = ABYTES + (wj * 64 + fr) * RB + slot;
+
+  for (int q = 0; q < NS - 1; ++q)
+    if (q < nk) issue(q);
   for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) load((it + 1) * BK);
-    const int ko = (lane >> 4) * 16;
-    const i4_t bf = *reinterpret_cast<const i4_t*>(&Bs[buf][(wave * 16 + (lane & 15)) * SK + ko]);
+    oz_wait_stages(min(nk - 1 - it, NS - 2));      // loads of step it have landed (this wave) ...
+    __syncthreads();                               // ... and every wave's; stage (it - 1) % NS is free
+    if (it + NS - 1 < nk) issue(it + NS - 1);
+    const int8_t* st = smem + (it % NS) * STAGE;
+    i4_t bf[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bf[c] = *reinterpret_cast<const i4_t*>(st + ob + c * 16 * RB);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+      const i4_t af = *reinterpret_cast<const i4_t*>(st + oa + s * BM * RB);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const i4_t af = *reinterpret_cast<const i4_t*>(&As[buf][s][(a * 16 + (lane & 15)) * SK + ko]);
-        acc[s][a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf, acc[s][a], 0, 0, 0);
-      }
+      for (int c = 0; c < 4; ++c) acc[s][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[c], af, acc[s][c], 0, 0, 0);
     }
-    if (it + 1 < nk) store(buf ^ 1);
-    __syncthreads();
   }
-  const int j = j0 + wave * 16 + (lane & 15);
-  if (j >= g.ncols) return;
+
+  const int i = i0 + wi * 16 + fr;
+  const int e = g.ex[i];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int c = 0; c < 4; ++c) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int i = i0 + a * 16 + 4 * (lane >> 4) + t;
-      const int e = g.ex[i];
+      const int j = j0 + wj * 64 + c * 16 + 4 * (lane >> 4) + t;
+      if (j >= g.ncols) continue;
       double v = 0.0;
 #pragma unroll
-      for (int s = S - 1; s >= 0; --s) v += ldexp((double)acc[s][a][t], e - 7 * (s + 1));
+      for (int s = S - 1; s >= 0; --s) v += ldexp((double)acc[s][c][t], e - 7 * (s + 1));
       g.C[(int64_t)i + (int64_t)j * g.ldc] = v;
     }
   }

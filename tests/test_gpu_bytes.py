@@ -55,7 +55,7 @@ def test_bytes_fp64_bitwise_equal_to_double_input():
 
 
 @pytest.mark.parametrize("n,p,m,bc,h2", [(512, 4, 2048, 2048, 0.5), (300, 3, 333, 100, 0.45), (1100, 8, 257, 257, 0.3),
-                                          (257, 1, 70, 64, 0.6)])
+                                          (257, 1, 70, 64, 0.6), (2900, 4, 1000, 1000, 0.4)])
 def test_int8_emulation_matches_oracle(n, p, m, bc, h2):
     Phi, XL, y, G = _inputs(n, p, m, n + p, "gauss" if p != 4 else "sex_age")
     ctx = GLSContext(_t(Phi), h2, _t(XL) if p > 1 else None, _t(y), block_cols=bc, precision="int8_emu")
