@@ -53,7 +53,8 @@ typedef enum {
   GLS_ERR_WORKSPACE = -4, /* workspace smaller than gls_workspace_bytes, or not
                              256-byte aligned                                     */
   GLS_ERR_STATE = -5,     /* call not valid in the handle's state                 */
-  GLS_ERR_RANK = -6       /* X_L rank deficient (S_TL not SPD); *info = 1-based
+  GLS_ERR_RANK = -6       /* X_L rank deficient: a squared pivot of S_TL at or
+                             below 2^-40 of its diagonal entry; *info = 1-based
                              covariate index                                      */
 } gls_status;
 

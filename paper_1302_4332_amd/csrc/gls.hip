@@ -217,7 +217,7 @@ static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
   double* Li = c->Linv;
   if (b - a == 1) {
     const int64_t r = (int64_t)a * NB_LEAF;
-    hipLaunchKernelGGL(leaf_potrf_trtri_kernel, dim3(1), dim3(256), 0, s, L + r + r * N, Li + r + r * N, N, (int)r,
+    hipLaunchKernelGGL(leaf_potrf_trtri_kernel, dim3(1), dim3(512), 0, s, L + r + r * N, Li + r + r * N, N, (int)r,
                        c->info);
     return;
   }

@@ -8,7 +8,7 @@
 namespace gls {
 
 // Leaf (diagonal block) size of the blocked Cholesky / inversion.
-constexpr int NB_LEAF = 64;
+constexpr int NB_LEAF = 128;
 
 // L <- M = h2 * Phi + (1 - h2) * I in the lower triangle of the leading n x n
 // block (read from Phi's lower triangle), identity on the padding rows
@@ -72,94 +72,213 @@ __device__ __forceinline__ double fast_rcp(double p) {
   return __builtin_fma(r, e, r);
 }
 
-// One diagonal block of the blocked factorization, entirely on chip:
-//   Cholesky of the NB_LEAF x NB_LEAF lower block at A (ld), right-looking.
-//   Each thread keeps its share of the trailing matrix in registers (column
-//   kc = t % 64, rows kc + t/64 + 4q, q < 16; entries past the block are
-//   dummies, so no per-entry branches).  At step j the owners of column j
-//   publish it (unscaled) into its own LDS column, one barrier per step, and
-//   every later column is updated with that column times 1/pivot.  The
-//   columns are scaled by 1/sqrt(pivot) after the loop, in parallel.
-//   Then the inverse of the factor, right-looking as well: lane jj holds
-//   column jj of the inverse in registers; at step k its entry k is scaled by
-//   1/L[k][k] and subtracted, times L[i][k], from every later entry i (the
-//   same terms, in the same order, as forward substitution).
-//   Writes the factor (zero upper part) back to A and the inverse (zero upper
-//   part) to Ainv (ld).  A non-positive or NaN pivot sets *info = row0 + j + 1
-//   if *info is still 0 (the 1-based global pivot; blocks run in order, so the
-//   first failure wins).
-__global__ __launch_bounds__(256) void leaf_potrf_trtri_kernel(double* __restrict__ A, double* __restrict__ Ainv,
+// One diagonal block of the blocked factorization, entirely on chip.
+//
+// The NB_LEAF x NB_LEAF block (128 x 128 doubles, 129 KB with the padded
+// column stride) sits in LDS and is processed as 8 x 8 blocks of 16 x 16:
+//   Cholesky, panel by panel (16 columns at a time):
+//     - one wave factors the 16 x 16 diagonal block (lane i owns row i; the
+//       column of each step is exchanged through LDS within the wave);
+//     - every row below solves against it (one thread per row, forward
+//       substitution with the stored 1 / L[k][k]);
+//     - the trailing lower blocks take the rank-16 update on
+//       v_mfma_f64_16x16x4f64; wave 0 updates the next diagonal block first
+//       and factors it while the other waves finish the update.
+//   Inverse, in place: the 16 x 16 diagonal inverses (one per wave), then
+//   block columns from right to left,
+//     X[i][j] = -(sum_{k=j+1..i} X[i][k] L[k][j]) X[j][j]   (i > j),
+//   again on 16 x 16 matrix-core products.
+// Block columns of the factor and of the inverse are written to A and Ainv
+// (ld, zeros above the diagonal) as soon as they are final.  A non-positive or
+// NaN pivot sets *info = row0 + j + 1 if *info is still 0 (the 1-based global
+// pivot; blocks run in order, so the first failure wins).
+
+typedef double l4_t __attribute__((ext_vector_type(4)));
+
+constexpr int LT = 16;                 // inner block size
+constexpr int LNB = NB_LEAF / LT;      // inner blocks per side
+constexpr int LD = NB_LEAF + 1;        // LDS column stride: odd, so 16 lanes reading along a row hit 16 banks
+static_assert(NB_LEAF % LT == 0 && LNB == 8, "the inverse's scratch blocks assume 8 x 8 inner blocks");
+
+__device__ __forceinline__ double* leaf_blk(double* S, int bi, int bj) { return S + (LT * bj) * LD + LT * bi; }
+
+// acc += op(A) op(B) for 16 x 16 blocks on v_mfma_f64_16x16x4f64.  A element
+// (r, k) at pa[r * ars + k * aks], B element (k, c) at pb[k * bks + c * bcs];
+// neg negates A.  Lane l supplies A[l % 16][4 s + l / 16] and
+// B[4 s + l / 16][l % 16]; the accumulator holds D[l / 16 + 4 t][l % 16].
+__device__ __forceinline__ void leaf_mma16(l4_t& acc, const double* pa, int ars, int aks, const double* pb, int bks,
+                                           int bcs, bool neg, int lane) {
+  const int r = lane & 15, q = lane >> 4;
+  double a[4], b[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    a[s] = pa[r * ars + (4 * s + q) * aks];
+    b[s] = pb[(4 * s + q) * bks + r * bcs];
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(neg ? -a[s] : a[s], b[s], acc, 0, 0, 0);
+}
+__device__ __forceinline__ l4_t leaf_ld_acc(const double* p, int lane) {
+  const int c = lane & 15, q = lane >> 4;
+  return l4_t{p[q + c * LD], p[q + 4 + c * LD], p[q + 8 + c * LD], p[q + 12 + c * LD]};
+}
+__device__ __forceinline__ void leaf_st_acc(double* p, l4_t v, int lane) {
+  const int c = lane & 15, q = lane >> 4;
+  p[q + c * LD] = v[0];
+  p[q + 4 + c * LD] = v[1];
+  p[q + 8 + c * LD] = v[2];
+  p[q + 12 + c * LD] = v[3];
+}
+
+// One wave factors the 16 x 16 diagonal block of panel p in place.  Lane i
+// (< 16) owns row i; at step j the column goes through LDS (the operations of
+// one wave on LDS complete in order; the empty asm statements with a memory
+// clobber stop the compiler from carrying values across the exchange).
+// Stores 1 / L[k][k] in rd[16 p + k]; returns the first non-positive pivot
+// (1-based within the leaf) or 0.
+__device__ __forceinline__ int leaf_factor16(double* S, int p, double* col, double* rd, int lane) {
+  const int i = lane & 15;
+  double* D = leaf_blk(S, p, p);
+  double w[LT];
+#pragma unroll
+  for (int k = 0; k < LT; ++k) w[k] = D[i + k * LD];
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < LT; ++j) {
+    if (lane < LT) col[i] = w[j];
+    asm volatile("" ::: "memory");
+    double c[LT];
+#pragma unroll
+    for (int k = j; k < LT; ++k) c[k] = col[k];
+    asm volatile("" ::: "memory");
+    const double d = c[j];
+    if (bad == 0 && !(d > 0.0)) bad = LT * p + j + 1;
+    const double sd = sqrt(d);
+    const double r = fast_rcp(sd);
+    const double lr = (i < j) ? 0.0 : w[j] * r * r;   // L[i][j] / L[j][j]
+    w[j] = (i < j) ? 0.0 : ((i == j) ? sd : w[j] * r);
+#pragma unroll
+    for (int k = j + 1; k < LT; ++k) w[k] -= lr * c[k];
+    if (lane == 0) rd[LT * p + j] = r;
+  }
+  if (lane < LT) {
+#pragma unroll
+    for (int k = 0; k < LT; ++k) D[i + k * LD] = w[k];
+  }
+  return bad;
+}
+
+// Block column q (columns 16 q .. 16 q + 15) of the lower triangle of S to G (ld), zeros above the diagonal.
+__device__ __forceinline__ void leaf_store_col(const double* S, double* G, int64_t ld, int q, int t) {
+  for (int idx = t; idx < NB_LEAF * LT; idx += 512) {
+    const int r = idx % NB_LEAF, c = LT * q + idx / NB_LEAF;
+    G[(int64_t)r + (int64_t)c * ld] = (r >= c) ? S[r + c * LD] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(512) void leaf_potrf_trtri_kernel(double* __restrict__ A, double* __restrict__ Ainv,
                                                                int64_t ld, int row0, int* __restrict__ info) {
-  constexpr int B = NB_LEAF;
-  constexpr int SC = 2 * B;   // column stride of lt (room for the dummy rows)
-  constexpr int S = B + 1;
-  constexpr int QR = B / 4;   // register rows per thread
-  static_assert(B == 64, "one lane per column of the block");
-  __shared__ double lt[B * SC];   // column j of the factor: lt[j * SC + i] = L[i][j]
-  __shared__ double rs[B];        // 1 / sqrt(pivot j) = 1 / L[j][j]
-  __shared__ double xo[B * S];    // inverse, column-major staging for the store
-  const int t = threadIdx.x;
-  const int kc = t & (B - 1);
-  const int r0 = t >> 6;
-  double a[QR];
-#pragma unroll
-  for (int q = 0; q < QR; ++q) {
-    const int i = kc + r0 + 4 * q;
-    a[q] = (i < B) ? A[(int64_t)i + (int64_t)kc * ld] : 0.0;
+  __shared__ __align__(16) double S[NB_LEAF * LD];
+  __shared__ double rd[NB_LEAF];   // 1 / L[k][k]
+  __shared__ double colw[LT];      // wave 0's column exchange
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int idx = t; idx < NB_LEAF * NB_LEAF; idx += 512) {
+    const int r = idx % NB_LEAF, c = idx / NB_LEAF;
+    S[r + c * LD] = A[(int64_t)r + (int64_t)c * ld];
   }
-  for (int j = 0; j < B; ++j) {
-    double* cj = lt + j * SC;
-    if (kc == j) {
+  __syncthreads();
+  int bad = 0;   // meaningful in wave 0
+  if (wave == 0) bad = leaf_factor16(S, 0, colw, rd, lane);
+  __syncthreads();
+  for (int p = 0; p < LNB; ++p) {
+    // rows below the diagonal block, one thread each:
+    //   L[r][16p + k] = (A[r][16p + k] - sum_{m<k} L[r][16p + m] L[16p + k][16p + m]) / L[16p + k][16p + k]
+    {
+      const int r = LT * (p + 1) + t;
+      if (r < NB_LEAF) {
+        const double* D = leaf_blk(S, p, p);
+        double* Pr = S + (LT * p) * LD + r;
+        double x[LT];
 #pragma unroll
-      for (int q = 0; q < QR; ++q) cj[kc + r0 + 4 * q] = a[q];
-    }
-    __syncthreads();
-    const double lk = (kc > j) ? cj[kc] * fast_rcp(cj[j]) : 0.0;
+        for (int k = 0; k < LT; ++k) x[k] = Pr[k * LD];
 #pragma unroll
-    for (int q = 0; q < QR; ++q) a[q] -= cj[kc + r0 + 4 * q] * lk;
-  }
-  if (t == 0) {
-    for (int j = 0; j < B; ++j) {
-      if (!(lt[j * SC + j] > 0.0)) {
-        if (*info == 0) *info = row0 + j + 1;
-        break;
+        for (int k = 0; k < LT; ++k) {
+          x[k] *= rd[LT * p + k];
+#pragma unroll
+          for (int m = k + 1; m < LT; ++m) x[m] -= x[k] * D[m + k * LD];
+        }
+#pragma unroll
+        for (int k = 0; k < LT; ++k) Pr[k * LD] = x[k];
       }
     }
+    __syncthreads();
+    leaf_store_col(S, A, ld, p, t);   // block column p of the factor is final
+    if (p == LNB - 1) break;
+    // trailing update A[i][c] -= L[i][p] L[c][p]^T for p < c <= i.  Task 0 is
+    // the next diagonal block: wave 0 updates it and factors it at once; waves
+    // 1..7 share the other tasks.
+    {
+      const int nb = LNB - 1 - p;
+      const int tasks = nb * (nb + 1) / 2;
+      for (int task = wave; task < tasks; task += (wave == 0) ? tasks : LNB - 1) {
+        int c = 0, rem = task;
+        while (rem >= nb - c) {
+          rem -= nb - c;
+          ++c;
+        }
+        const int bc = p + 1 + c, bi = bc + rem;
+        double* C = leaf_blk(S, bi, bc);
+        l4_t acc = leaf_ld_acc(C, lane);
+        leaf_mma16(acc, leaf_blk(S, bi, p), 1, LD, leaf_blk(S, bc, p), LD, 1, true, lane);
+        leaf_st_acc(C, acc, lane);
+      }
+      if (wave == 0) {
+        const int b = leaf_factor16(S, p + 1, colw, rd, lane);
+        if (bad == 0) bad = b;
+      }
+    }
+    __syncthreads();
   }
-  if (t < B) rs[t] = 1.0 / sqrt(lt[t * SC + t]);
+  if (wave == 0 && lane == 0 && bad != 0 && *info == 0) *info = row0 + bad;
   __syncthreads();
-  for (int idx = t; idx < B * B; idx += blockDim.x) {
-    const int i = idx % B, j = idx / B;
-    if (i > j) lt[j * SC + i] *= rs[j];
-    else if (i == j) lt[j * SC + i] = sqrt(lt[j * SC + i]);
-  }
-  __syncthreads();
-  for (int idx = t; idx < B * B; idx += blockDim.x) {
-    const int i = idx % B, k = idx / B;
-    A[(int64_t)i + (int64_t)k * ld] = (i >= k) ? lt[k * SC + i] : 0.0;
-  }
-  if (t < B) {
-    // Sliding window: before step k, w[d] holds entry k + d of the lane's
-    // column (entries past the block are dummies, never stored).  A runtime
-    // loop over k keeps the code small: straight-line code run once would be
-    // bound by instruction fetch.
-    const int jj = t;
-    double w[B];
+  // the 16 x 16 diagonal inverses, in place: wave w takes block w, lane c < 16 forms column c
+  {
+    const int c = lane & 15;
+    double* D = leaf_blk(S, wave, wave);
+    double x[LT];
 #pragma unroll
-    for (int d = 0; d < B; ++d) w[d] = (d == jj) ? 1.0 : 0.0;
-    for (int k = 0; k < B; ++k) {
-      const double xk = w[0] * rs[k];
-      xo[k + jj * S] = xk;
-      const double* lk = lt + k * SC + k;   // L[k + d][k] for d >= 1 (rows past the block: dummies)
+    for (int k = 0; k < LT; ++k) x[k] = (k == c) ? 1.0 : 0.0;
 #pragma unroll
-      for (int d = 1; d < B; ++d) w[d - 1] = w[d] - lk[d] * xk;
-      w[B - 1] = 0.0;
+    for (int k = 0; k < LT; ++k) {
+      x[k] *= rd[LT * wave + k];
+#pragma unroll
+      for (int m = k + 1; m < LT; ++m) x[m] -= D[m + k * LD] * x[k];
+    }
+    if (lane < LT) {
+#pragma unroll
+      for (int k = 0; k < LT; ++k) D[k + c * LD] = x[k];
     }
   }
   __syncthreads();
-  for (int idx = t; idx < B * B; idx += blockDim.x) {
-    const int i = idx % B, k = idx / B;
-    Ainv[(int64_t)i + (int64_t)k * ld] = xo[i + k * S];
+  leaf_store_col(S, Ainv, ld, LNB - 1, t);
+  // block columns of the inverse, right to left; T goes to a scratch block of
+  // the strictly upper triangle (never read as data)
+  for (int j = LNB - 2; j >= 0; --j) {
+    const int bi = j + 1 + wave;
+    double* T = (wave < LNB - 1) ? leaf_blk(S, wave, LNB - 1) : leaf_blk(S, 0, LNB - 2);
+    l4_t acc = {0.0, 0.0, 0.0, 0.0};
+    if (bi < LNB) {
+      for (int k = j + 1; k <= bi; ++k) leaf_mma16(acc, leaf_blk(S, bi, k), 1, LD, leaf_blk(S, k, j), 1, LD, false, lane);
+      leaf_st_acc(T, acc, lane);
+    }
+    __syncthreads();
+    if (bi < LNB) {
+      acc = l4_t{0.0, 0.0, 0.0, 0.0};
+      leaf_mma16(acc, T, 1, LD, leaf_blk(S, j, j), 1, LD, true, lane);
+      leaf_st_acc(leaf_blk(S, bi, j), acc, lane);
+    }
+    __syncthreads();
+    leaf_store_col(S, Ainv, ld, j, t);   // block column j of the inverse is final
   }
 }
 
@@ -200,8 +319,15 @@ struct SmallLayout {
   static __host__ __device__ int size(int p) { return qres(p) + 1; }
 };
 
+// Relative pivot floor of the covariate factorization: X_L counts as rank
+// deficient when a squared pivot of S_TL falls to 2^-40 of its diagonal entry
+// or below (exactly collinear covariates leave a rounding residual of either
+// sign, about 1e-16 of it).
+constexpr double RANK_REL = 9.094947017729282e-13;  // 2^-40
+
 // Single-thread factorization of S_TL = G[0:q, 0:q] and the hoisted
-// right-hand side.  Sets *info_rank = j + 1 for the first non-positive pivot.
+// right-hand side.  Sets *info_rank = j + 1 for the first pivot at or below
+// the floor.
 __global__ void small_factor_kernel(const double* __restrict__ G, int p, double* __restrict__ small,
                                     int* __restrict__ info_rank) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -211,7 +337,7 @@ __global__ void small_factor_kernel(const double* __restrict__ G, int p, double*
   for (int j = 0; j < q; ++j) {
     double d = G[j + j * p];
     for (int k = 0; k < j; ++k) d -= Lt[j + k * q] * Lt[j + k * q];
-    if (!(d > 0.0) && *info_rank == 0) *info_rank = j + 1;
+    if (!(d > RANK_REL * G[j + j * p]) && *info_rank == 0) *info_rank = j + 1;
     d = sqrt(d);
     Lt[j + j * q] = d;
     for (int i = j + 1; i < q; ++i) {
