@@ -71,6 +71,22 @@ def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
     ost = O.Study(st.Phi, h2, st.XL, st.y)
     samp = np.r_[np.arange(512), np.arange(m - 64, m)]
     ref = ost.block(np.concatenate([st.snps(0, 512), st.snps(m - 64, m)]).T)
+    # error of b against the oracle after 0..4 refinement sweeps, on the sample
+    Xs_d = torch.tensor(np.concatenate([st.snps(0, 512), st.snps(m - 64, m)]), device=dev)
+    ok = ref["status"] == 0
+    by_sweeps = {}
+    for prec in ("fp32_ir", "fp16_ir", "bf16_ir"):
+        errs = []
+        for k in range(5):
+            ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=Xs_d.shape[0], precision=prec, refine_sweeps=k)
+            gb = ctx.block(Xs_d)[0].cpu().numpy()
+            ctx.close()
+            errs.append(float((np.max(np.abs(gb[ok] - ref["b"][ok]), axis=1) / np.max(np.abs(ref["b"][ok]), axis=1)).max()))
+        by_sweeps[prec] = errs
+        log(f"{prec} max rel err of b after 0..4 sweeps: " + ", ".join(f"{e:.1e}" for e in errs))
+    res["max_rel_err_b_by_sweeps"] = {"sweeps": [0, 1, 2, 3, 4], **by_sweeps,
+                                      "sample": "SNPs [0, 512) and the last 64, against the oracle"}
+    del Xs_d
     for prec, sweeps in (("fp32_ir", 1), ("fp16_ir", 3), ("bf16_ir", 4)):
         b_d = torch.empty((m, p), dtype=torch.float64, device=dev)
         s2_d = torch.empty(m, dtype=torch.float64, device=dev)
@@ -240,7 +256,7 @@ def main():
     import torch
 
     from paper_1302_4332_amd import synth
-    from paper_1302_4332_amd.gls import GLSContext
+    from paper_1302_4332_amd.gls import GLSContext, make_opts, workspace_bytes
 
     w = synth.WORKLOADS[args.workload]
     m = args.m or w.m
@@ -344,6 +360,9 @@ def main():
         "phases_ms_per_step": {k: v[1] / args.steps for k, v in phase_tot.items()},
         "setup_ms": setup_ms,
         "snps_per_s_excl_setup": m / ((ms_per_step - setup_ms) / 1e3) if ms_per_step > setup_ms else None,
+        "device_memory": {"peak_allocated_bytes": int(torch.cuda.max_memory_allocated()),
+                          "workspace_bytes": workspace_bytes(n, p, make_opts(bc, args.precision, args.sweeps)),
+                          "snp_matrix_bytes": int(X_d.numel() * 8)},
     }
 
     if not args.no_forms:
