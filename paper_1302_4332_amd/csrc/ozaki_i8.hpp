@@ -136,14 +136,22 @@ __device__ __forceinline__ void oz_load_lds16(const void* src, uint32_t lds) {
       : "memory");
 }
 
-// wait until at most 4 n of this wave's global-to-LDS loads are in flight
-// (n whole stages: four load instructions each)
+// wait until at most n whole stages (L load instructions each) of this wave's
+// global-to-LDS loads are in flight
+template <int L>
 __device__ __forceinline__ void oz_wait_stages(int n) {
-  switch (n) {
-    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-    case 1: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
-    case 2: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
-    default: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+  static_assert(L == 4 || L == 6, "wait counts");
+  if (n <= 0) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else if (n == 1) {
+    if (L == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+  } else if (n == 2) {
+    if (L == 4) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+  } else {
+    if (L == 4) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
   }
 }
 
@@ -153,7 +161,8 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   constexpr int ABYTES = S * BM * RB, STAGE = ABYTES + BN * RB;
   constexpr int QA = S * BM / 16 / NW;           // 1 KB load instructions per wave and stage
   constexpr int QB = BN / 16 / NW;
-  static_assert(BK == 64 && QA == 2 && QB == 2 && NS >= 2 && NS <= 5, "loader and wait counts assume this split");
+  static_assert(BK == 64 && BM == 32 && NW == 2 * (BN / 64), "two 16-row strips x BN / 64 column strips of waves");
+  static_assert(QA * 16 * NW == S * BM && QB * 16 * NW == BN && NS >= 2 && NS <= 5, "loader split");
   static_assert(NS * STAGE <= 160 * 1024, "LDS");
   __shared__ __align__(1024) int8_t smem[NS * STAGE];
 
@@ -213,7 +222,7 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   for (int q = 0; q < NS - 1; ++q)
     if (q < nk) issue(q);
   for (int it = 0; it < nk; ++it) {
-    oz_wait_stages(min(nk - 1 - it, NS - 2));      // loads of step it have landed (this wave) ...
+    oz_wait_stages<QA + QB>(min(nk - 1 - it, NS - 2));   // loads of step it have landed (this wave) ...
     __syncthreads();                               // ... and every wave's; stage (it - 1) % NS is free
     if (it + NS - 1 < nk) issue(it + NS - 1);
     const int8_t* st = smem + (it % NS) * STAGE;
