@@ -148,6 +148,10 @@ typedef struct {
  * `compute_stream`, and the results are copied into the host arrays
  * b_host (p x m, ld = p), sigma2_host, v_host, status_host at the same
  * column offsets.  Blocks of opts.block_cols columns; the last one is ragged.
+ * With block_cols >= 2,048 the stream starts with shorter blocks
+ * (block_cols / 8, growing by a quarter per block, multiples of 64), so the
+ * first copy, which nothing overlaps, is short; results are bitwise the same
+ * for any blocking.
  * Returns after every result has landed.  col0 > 0 resumes an interrupted
  * run: outputs for columns < col0 are not touched. */
 gls_status gls_stream(gls_handle h, int64_t m, int64_t col0,

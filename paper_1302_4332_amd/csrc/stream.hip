@@ -11,6 +11,7 @@
 #include <fcntl.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <cerrno>
 #include <chrono>
 #include <condition_variable>
@@ -75,7 +76,23 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
   hipStream_t sx = (c->opts.flags & GLS_STREAM_SERIAL) ? sc : static_cast<hipStream_t>(copy_stream);
   const int64_t n = c->n, bc = c->bc;
   const int p = c->p;
-  const int64_t nblk = (m - col0 + bc - 1) / bc;
+  // Block schedule.  Full blocks of bc, except that a stream of large blocks
+  // (bc >= 2,048) starts with short ones, bc / 8 growing by a quarter per
+  // block (multiples of 64): the first copy, which nothing overlaps, is an
+  // eighth as long, and each later copy still fits under the solve before it
+  // (a solve takes longer per SNP than its copy).  Results do not depend on
+  // the blocking.
+  std::vector<int64_t> bstart;
+  {
+    int64_t pos = 0, len = (bc >= 2048) ? std::max<int64_t>(64, bc / 8 / 64 * 64) : bc;
+    while (pos < m - col0) {
+      bstart.push_back(pos);
+      pos += std::min(len, m - col0 - pos);
+      len = std::min(bc, (len * 5 / 4 + 63) / 64 * 64);
+    }
+    bstart.push_back(m - col0);
+  }
+  const int64_t nblk = (int64_t)bstart.size() - 1;
   gls_stream_stats st{};
   if (nblk == 0) {
     if (stats_out) *stats_out = st;
@@ -87,8 +104,8 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
   if ((e = pool.make(2 * nblk + 2)) != hipSuccess) return hip_fail(e, "gls_stream: event create");
   hipEvent_t wall0 = pool.ev[2 * nblk], wall1 = pool.ev[2 * nblk + 1];
 
-  auto cols_of = [&](int64_t blk) { return std::min<int64_t>(bc, m - col0 - blk * bc); };
-  auto src_of = [&](int64_t blk) { return XR_host + (col0 + blk * bc) * ld_xr; };
+  auto cols_of = [&](int64_t blk) { return bstart[blk + 1] - bstart[blk]; };
+  auto src_of = [&](int64_t blk) { return XR_host + (col0 + bstart[blk]) * ld_xr; };
 
   if ((e = hipEventRecord(wall0, sx)) != hipSuccess) return hip_fail(e, "gls_stream: record");
   if ((e = h2d_block(stage(c, 0, XR_host), n, src_of(0), ld_xr, cols_of(0), sx)) != hipSuccess)
@@ -99,7 +116,7 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
   for (int64_t blk = 0; blk < nblk; ++blk) {
     const int cur = (int)(blk & 1), nxt = cur ^ 1;
     const int64_t cols = cols_of(blk);
-    const int64_t col = col0 + blk * bc;
+    const int64_t col = col0 + bstart[blk];
     if (blk + 1 < nblk && sx != sc) {
       // beta may only be overwritten once the solve that last read it is done
       if (blk >= 1 && (e = hipStreamWaitEvent(sx, c->ev_comp[nxt], 0)) != hipSuccess)

@@ -162,3 +162,31 @@ def test_serial_stream_equals_overlapped():
     (rb, _, _, sb), stats = b.stream(host)
     assert stats.blocks == 6 and stats.h2d_bytes == 8 * 330 * 700
     assert np.array_equal(ra.numpy(), rb.numpy()) and np.array_equal(sa.numpy(), sb.numpy())
+
+
+def _ramp_blocks(m, col0, bc):
+    """Block count of the stream's schedule: with bc >= 2,048 it opens with
+    bc / 8 and grows by a quarter per block (multiples of 64) up to bc."""
+    pos, ln, k = 0, (max(64, bc // 8 // 64 * 64) if bc >= 2048 else bc), 0
+    while pos < m - col0:
+        pos += min(ln, m - col0 - pos)
+        ln = min(bc, (ln * 5 // 4 + 63) // 64 * 64)
+        k += 1
+    return k
+
+
+def test_stream_ramp_bitwise():
+    """Large blocks: the stream opens with shorter blocks; results stay bitwise
+    those of full blocks, also on resume in the middle of the ramp."""
+    Phi, h2, XL, y, XR = _problem(300, 4, 9000, seed=25)
+    bc = 2048
+    ref = _gpu(Phi, h2, XL, y, XR, bc)
+    ctx = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=bc)
+    host = torch.tensor(XR).pin_memory()
+    (b, s2, v, st), stats = ctx.stream(host)
+    assert stats.blocks == _ramp_blocks(9000, 0, bc) == 10
+    assert np.array_equal(b.numpy(), ref["b"]) and np.array_equal(s2.numpy(), ref["sigma2"])
+    assert np.array_equal(v.numpy(), ref["v"]) and np.array_equal(st.numpy(), ref["status"])
+    (b2, _, _, st2), stats2 = ctx.stream(host, col0=300)
+    assert stats2.blocks == _ramp_blocks(9000, 300, bc)
+    assert np.array_equal(b2.numpy()[300:], ref["b"][300:]) and np.array_equal(st2.numpy()[300:], ref["status"][300:])
