@@ -625,14 +625,14 @@ static void lp_solve_t(Ctx* c, const double* src, int64_t lds, int mb, double be
   a.ncols = mb;
   a.K = (int)N;
   a.beta = beta;
-  a.map_gm = 1;
-  a.map_gn = 16;
+  a.map_gm = 2;
+  a.map_gn = 8;
   a.map_desc = 1;
-  const int Mt = (int)(N / 64), Nt = (mb + 63) / 64;
+  const int Mt = (int)(N / LP_BM), Nt = (mb + LP_BN - 1) / LP_BN;
   GemmArgs m{};
-  m.map_gm = 1;
-  m.map_gn = 16;
-  hipLaunchKernelGGL(lp_gemm_kernel<T>, dim3(XcdMap::grid(m, Mt, Nt)), dim3(256), 0, s, a);
+  m.map_gm = a.map_gm;
+  m.map_gn = a.map_gn;
+  hipLaunchKernelGGL(lp_gemm_kernel<T>, dim3(XcdMap::grid(m, Mt, Nt)), dim3(LP_THREADS), 0, s, a);
 }
 
 // Xt (N x mb) = L^-1 src in the handle's low precision with FP32 accumulation;

@@ -13,16 +13,13 @@
 #include <stdint.h>
 
 #include "gemm_f64.hpp"
+#include "lds_dma.hpp"
 
 namespace gls {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
-
-// Row of the accumulator element t held by lane l in the 16x16 FP32-output
-// MFMA forms (checked on gfx950 with known operands).
-__device__ __forceinline__ int lp_acc_row(int lane, int t) { return 4 * (lane >> 4) + t; }
 
 struct LpArgs {
   const void* A; int64_t lda;     // row-major: A[i * lda + k]
@@ -35,54 +32,64 @@ struct LpArgs {
   int map_gm, map_gn, map_desc;   // as GemmArgs (XCD mapping, lower-triangular A)
 };
 
+// One 16-byte chunk of k per lane and operand feeds SUB matrix-core
+// instructions.  Operand layouts (gfx950): in the 16x16 forms lane l holds
+// row (or column) l % 16 of its operand; for FP16/BF16 (16x16x32) the chunk is
+// the 8 consecutive k at 8 (l / 16), one instruction; for FP32 (16x16x4, one k
+// per lane) element s of the chunk feeds instruction s, i.e. instruction s
+// sums k = 4 (l / 16) + s over the four lane groups (a permutation of k that
+// both operands share, so the sum is the same).  Accumulator element t is
+// D[4 (l / 16) + t][l % 16].
 template <typename T> struct LpMfma;
 
 template <> struct LpMfma<float> {
-  static constexpr int KSTEP = 4;   // k per instruction
-  static constexpr int KPL = 1;     // k per lane
-  __device__ static f4_t mma(const float* a, const float* b, f4_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  static constexpr int SUB = 4;
+  __device__ static f4_t mma(uint4 a, uint4 b, f4_t c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+    return c;
   }
 };
 template <> struct LpMfma<_Float16> {
-  static constexpr int KSTEP = 32;
-  static constexpr int KPL = 8;
-  __device__ static f4_t mma(const _Float16* a, const _Float16* b, f4_t c) {
-    h8_t av, bv;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) { av[e] = a[e]; bv[e] = b[e]; }
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
+  static constexpr int SUB = 1;
+  __device__ static f4_t mma(uint4 a, uint4 b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8_t, a), __builtin_bit_cast(h8_t, b), c, 0, 0, 0);
   }
 };
 template <> struct LpMfma<__bf16> {
-  static constexpr int KSTEP = 32;
-  static constexpr int KPL = 8;
-  __device__ static f4_t mma(const __bf16* a, const __bf16* b, f4_t c) {
-    b8_t av, bv;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) { av[e] = a[e]; bv[e] = b[e]; }
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  static constexpr int SUB = 1;
+  __device__ static f4_t mma(uint4 a, uint4 b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8_t, a), __builtin_bit_cast(b8_t, b), c, 0, 0,
+                                                  0);
   }
 };
 
-// 64 x 64 tiles, BK = 64 k per LDS slice, four waves each owning a 64 x 16
-// strip (four 16x16 accumulators).  Both operands are k-contiguous in global
-// memory and in LDS (As[i][k], Bs[j][k]); 16-byte vector moves.  Requires
-// 16-byte aligned A/B, lda and ldb multiples of 8 elements, K a multiple of
-// BK (the callers pad every operand).
+// Tiles of 256 rows of A x 128 columns of B; eight waves, each a 64 x 64
+// block (4 x 4 accumulators of 16 x 16).  Each stage covers 128 bytes of k per
+// row (64 FP16/BF16 or 32 FP32 values); the 256 + 128 rows of a stage move
+// straight from global memory into a ring of three LDS buffers (1 KB, eight
+// rows, per wave instruction; two stages in flight ahead of the MFMAs).
+// Chunk c of LDS row r sits in slot c ^ lp_swz(r): eight consecutive lanes of a
+// fragment read fall on distinct 128-byte bank lines, sixteen on distinct
+// 256-byte lines.  The product is formed transposed (B's columns as the
+// instruction's first operand) so that the FP64 stores of C run down columns.
+// Requires 16-byte aligned A and B, lda and ldb multiples of 8 elements and K
+// a multiple of 64 (the callers pad every operand to N, a multiple of 256).
+constexpr int LP_BM = 256, LP_BN = 128, LP_RB = 128, LP_THREADS = 512, LP_STAGES = 3;
+
+__device__ __forceinline__ int lp_swz(int r) { return (r ^ (r >> 3)) & 7; }
+
 template <typename T>
-__global__ __launch_bounds__(256) void lp_gemm_kernel(LpArgs g) {
-  constexpr int BM = 64, BN = 64, BK = 64;
-  constexpr int VE = 16 / sizeof(T);           // elements per 16-byte move
-  constexpr int PAD = VE;                      // keeps rows 16-byte aligned, staggers banks
-  constexpr int SK = BK + PAD;
-  constexpr int KSTEP = LpMfma<T>::KSTEP;
-  constexpr int KPL = LpMfma<T>::KPL;
-  constexpr int CH = BM * BK / VE;             // 16-byte chunks per operand slice
-  constexpr int PER = CH / 256;
-  static_assert(CH % 256 == 0, "loader");
-  __shared__ T As[2][BM * SK];
-  __shared__ T Bs[2][BN * SK];
+__global__ __launch_bounds__(LP_THREADS) void lp_gemm_kernel(LpArgs g) {
+  constexpr int BM = LP_BM, BN = LP_BN, RB = LP_RB, NW = LP_THREADS / 64, NS = LP_STAGES;
+  constexpr int BKE = RB / (int)sizeof(T);   // k per stage
+  constexpr int STAGE = (BM + BN) * RB;      // bytes
+  constexpr int NLD = (BM + BN) / 8 / NW;    // load instructions per wave and stage
+  static_assert(NLD * 8 * NW == BM + BN && BM == 4 * 64 && BN == 2 * 64 && NW == 8, "tile split");
+  static_assert(NS * STAGE <= 160 * 1024, "LDS");
+  __shared__ __align__(1024) char smem[NS * STAGE];
 
   int ti, tj;
   {
@@ -95,71 +102,93 @@ __global__ __launch_bounds__(256) void lp_gemm_kernel(LpArgs g) {
   }
   const int i0 = ti * BM, j0 = tj * BN;
   const int khi = (i0 + BM < g.K) ? i0 + BM : g.K;   // A lower triangular
-  const int nk = (khi + BK - 1) / BK;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const T* A = static_cast<const T*>(g.A);
-  const T* B = static_cast<const T*>(g.B);
+  const int nk = (khi + BKE - 1) / BKE;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave & 3, wj = wave >> 2;
+  const char* A = static_cast<const char*>(g.A);
+  const char* B = static_cast<const char*>(g.B);
 
-  f4_t acc[4];
+  // loader: instruction q of this wave fills stage rows 8 (q NW + wave) .. +7
+  // (rows < BM: A's rows i0.., then B's columns j0..; columns past the end read
+  // the last valid one, whose results are dropped)
+  const char* src[NLD];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) acc[a] = f4_t{0.f, 0.f, 0.f, 0.f};
-
-  uint4 ra[PER], rb[PER];
-  auto load = [&](int kt) {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int c = tid + e * 256;
-      const int r = c / (BK / VE), kc = (c % (BK / VE)) * VE;
-      ra[e] = *reinterpret_cast<const uint4*>(A + (int64_t)(i0 + r) * g.lda + kt + kc);
-      rb[e] = *reinterpret_cast<const uint4*>(B + (int64_t)(kt + kc) + (int64_t)(j0 + r) * g.ldb);
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int c = tid + e * 256;
-      const int r = c / (BK / VE), kc = (c % (BK / VE)) * VE;
-      *reinterpret_cast<uint4*>(&As[buf][r * SK + kc]) = ra[e];
-      *reinterpret_cast<uint4*>(&Bs[buf][r * SK + kc]) = rb[e];
-    }
-  };
-  if (nk > 0) {
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int it = 0; it < nk; ++it) {
-      const int buf = it & 1;
-      if (it + 1 < nk) load((it + 1) * BK);
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += KSTEP) {
-        const int ko = kk + (lane >> 4) * KPL;
-        T bf[KPL];
-#pragma unroll
-        for (int e = 0; e < KPL; ++e) bf[e] = Bs[buf][(wave * 16 + (lane & 15)) * SK + ko + e];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          T af[KPL];
-#pragma unroll
-          for (int e = 0; e < KPL; ++e) af[e] = As[buf][(a * 16 + (lane & 15)) * SK + ko + e];
-          acc[a] = LpMfma<T>::mma(af, bf, acc[a]);
-        }
-      }
-      if (it + 1 < nk) store(buf ^ 1);
-      __syncthreads();
+  for (int q = 0; q < NLD; ++q) {
+    const int r = 8 * (q * NW + wave) + (lane >> 3);
+    const int chunk = (lane & 7) ^ lp_swz(r);
+    if (r < BM) {
+      src[q] = A + ((int64_t)(i0 + r) * g.lda) * (int64_t)sizeof(T) + 16 * chunk;
+    } else {
+      const int j = min(j0 + r - BM, g.ncols - 1);
+      src[q] = B + ((int64_t)j * g.ldb) * (int64_t)sizeof(T) + 16 * chunk;
     }
   }
-  const int j = j0 + wave * 16 + (lane & 15);
-  if (j >= g.ncols) return;
-  const double cs = g.cscale[j];
+  const uint32_t lds0 = lds_address(smem);
+  auto issue = [&](int kstep) {
+    const uint32_t base = lds0 + (uint32_t)((kstep % NS) * STAGE);
+    const int64_t kb = (int64_t)kstep * RB;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+    for (int q = 0; q < NLD; ++q)
+      lds_load16(src[q] + kb, __builtin_amdgcn_readfirstlane(base + 1024 * (q * NW + wave)));
+  };
+
+  // fragment offsets within a stage: span h (64 bytes of k), lane group lane >> 4
+  int offa[4][2], offb[4][2];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int ra = wi * 64 + f * 16 + (lane & 15), rb = BM + wj * 64 + f * 16 + (lane & 15);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 4 * h + (lane >> 4);
+      offa[f][h] = ra * RB + 16 * (c ^ lp_swz(ra));
+      offb[f][h] = rb * RB + 16 * (c ^ lp_swz(rb));
+    }
+  }
+
+  f4_t acc[4][4];   // [column block][row block], transposed 16 x 16 products
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[b][a] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  for (int q = 0; q < NS - 1; ++q)
+    if (q < nk) issue(q);
+  for (int it = 0; it < nk; ++it) {
+    wait_stages<NLD>(min(nk - 1 - it, NS - 2));   // this wave's loads of stage it have landed ...
+    __syncthreads();                              // ... and every wave's; stage (it - 1) % NS is free
+    if (it + NS - 1 < nk) issue(it + NS - 1);
+    const char* st = smem + (it % NS) * STAGE;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint4 fa[4], fb[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        fa[f] = *reinterpret_cast<const uint4*>(st + offa[f][h]);
+        fb[f] = *reinterpret_cast<const uint4*>(st + offb[f][h]);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[b][a] = LpMfma<T>::mma(fb[b], fa[a], acc[b][a]);
+    }
+  }
+
+  // acc[b][a][t] = C[i0 + wi 64 + 16 a + lane % 16][j0 + wj 64 + 16 b + 4 (lane / 16) + t]
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int i = i0 + a * 16 + lp_acc_row(lane, t);
-      if (i >= g.mvalid) continue;
-      double v = cs * (double)acc[a][t];
-      if (g.beta != 0.0) v += g.beta * g.Cin[(int64_t)i + (int64_t)j * g.ldcin];
-      g.C[(int64_t)i + (int64_t)j * g.ldc] = v;
+      const int j = j0 + wj * 64 + b * 16 + 4 * (lane >> 4) + t;
+      if (j >= g.ncols) continue;
+      const double cs = g.cscale[j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = i0 + wi * 64 + a * 16 + (lane & 15);
+        if (i >= g.mvalid) continue;
+        double v = cs * (double)acc[b][a][t];
+        if (g.beta != 0.0) v += g.beta * g.Cin[(int64_t)i + (int64_t)j * g.ldcin];
+        g.C[(int64_t)i + (int64_t)j * g.ldc] = v;
+      }
     }
   }
 }

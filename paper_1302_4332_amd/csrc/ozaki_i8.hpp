@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include "gemm_f64.hpp"
+#include "lds_dma.hpp"
 
 namespace gls {
 
@@ -107,9 +108,7 @@ struct OzArgs {
 //
 // Operands reach LDS by direct global-to-LDS loads (global_load_lds_dwordx4:
 // no staging registers) into a ring of OZ_STAGES buffers, OZ_STAGES - 1 steps
-// ahead of the MFMAs.  The loads are issued from inline assembly so that the
-// compiler does not drain them at every barrier; the kernel waits on vmcnt
-// itself.  One load instruction moves 1 KB: sixteen 64-byte rows, lane l
+// ahead of the MFMAs (see lds_dma.hpp).  One load instruction moves 1 KB: sixteen 64-byte rows, lane l
 // writing bytes [16 l, 16 l + 16) of it.  Chunk c of row r is stored in slot
 // c ^ oz_swz(r), so that a fragment read (sixteen rows, one chunk each) puts
 // every eight consecutive lanes on distinct 128-byte bank lines and all sixteen
@@ -117,43 +116,6 @@ struct OzArgs {
 constexpr int OZ_BM = 32, OZ_BN = 256, OZ_BK = 64, OZ_THREADS = 512, OZ_STAGES = 4;
 
 __device__ __forceinline__ int oz_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
-
-__device__ __forceinline__ uint32_t oz_lds_address(const void* p) {
-  return (uint32_t)(uintptr_t)((const __attribute__((address_space(3))) char*)p);
-}
-
-// 16 bytes per lane from global memory to LDS at lds + 16 * lane (lds: wave-uniform).
-// M0 carries the LDS address; it is saved and restored around the load.
-__device__ __forceinline__ void oz_load_lds16(const void* src, uint32_t lds) {
-  uint32_t keep;
-  asm volatile(
-      "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %2\n\t"
-      "global_load_lds_dwordx4 %1, off\n\t"
-      "s_mov_b32 m0, %0"
-      : "=&s"(keep)
-      : "v"(src), "s"(lds)
-      : "memory");
-}
-
-// wait until at most n whole stages (L load instructions each) of this wave's
-// global-to-LDS loads are in flight
-template <int L>
-__device__ __forceinline__ void oz_wait_stages(int n) {
-  static_assert(L == 4 || L == 6, "wait counts");
-  if (n <= 0) {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  } else if (n == 1) {
-    if (L == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-  } else if (n == 2) {
-    if (L == 4) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
-  } else {
-    if (L == 4) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
-  }
-}
 
 __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   constexpr int BM = OZ_BM, BN = OZ_BN, BK = OZ_BK, S = OZ_SLICES, NW = OZ_THREADS / 64, NS = OZ_STAGES;
@@ -195,16 +157,16 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
     const int j = min(j0 + 16 * (q * NW + wave) + lrow, g.ncols - 1);   // columns past the end: any valid
     pb[q] = g.B + (int64_t)j * g.N + lchunk;                            // column, their results are dropped
   }
-  const uint32_t lds0 = oz_lds_address(smem);
+  const uint32_t lds0 = lds_address(smem);
   auto issue = [&](int kstep) {
     const uint32_t base = lds0 + (uint32_t)((kstep % NS) * STAGE);
     const int kt = kstep * BK;
 #pragma unroll
     for (int q = 0; q < QA; ++q)
-      oz_load_lds16(pa[q] + kt, __builtin_amdgcn_readfirstlane(base + 1024 * (q * NW + wave)));
+      lds_load16(pa[q] + kt, __builtin_amdgcn_readfirstlane(base + 1024 * (q * NW + wave)));
 #pragma unroll
     for (int q = 0; q < QB; ++q)
-      oz_load_lds16(pb[q] + kt, __builtin_amdgcn_readfirstlane(base + ABYTES + 1024 * (q * NW + wave)));
+      lds_load16(pb[q] + kt, __builtin_amdgcn_readfirstlane(base + ABYTES + 1024 * (q * NW + wave)));
   };
 
   i4_t acc[S][4];
@@ -222,7 +184,7 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   for (int q = 0; q < NS - 1; ++q)
     if (q < nk) issue(q);
   for (int it = 0; it < nk; ++it) {
-    oz_wait_stages<QA + QB>(min(nk - 1 - it, NS - 2));   // loads of step it have landed (this wave) ...
+    wait_stages<QA + QB>(min(nk - 1 - it, NS - 2));   // loads of step it have landed (this wave) ...
     __syncthreads();                               // ... and every wave's; stage (it - 1) % NS is free
     if (it + NS - 1 < nk) issue(it + NS - 1);
     const int8_t* st = smem + (it % NS) * STAGE;
