@@ -34,11 +34,12 @@ TRAFFIC_RECORD = {"kernel_sha1": "ecc29e99b69e7c62", "n": 10000, "block_cols": 8
 
 
 def kernel_hash() -> str:
+    """Hash of the sources of the per-block product kernel (traffic records apply to one version)."""
     import hashlib
-    a = open(os.path.join(ROOT, "paper_1302_4332_amd", "csrc", "gemm_f64.hpp"), "rb").read()
-    g = open(os.path.join(ROOT, "paper_1302_4332_amd", "csrc", "gls.hip")).read()
-    line = [l for l in g.splitlines() if l.startswith("constexpr int GBM")][0]
-    return hashlib.sha1(a + line.encode()).hexdigest()[:16]
+    h = hashlib.sha1()
+    for f in ("gemm_f64.hpp", "gemm_f64_dma.hpp", "lds_dma.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1302_4332_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -347,7 +348,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None, "traffic": traffic,
                 "traffic_unit": "bytes per full 8,192-SNP launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE, calibrated)",
-                "kernel": "gemm_f64_kernel<64,64,16,1,4,false,false,MAP_XCD,VEC,M4> (X~ = L^-1 X)",
+                "kernel": "trmm_f64_dma_kernel (X~ = L^-1 X; 128 x 64 tiles, v_mfma_f64_4x4x4_4b_f64)",
                 "launch_ms_avg": wms / wl if wl else None, "launches": wl,
                 "flops_per_snp": float(n) * n}
     out = {

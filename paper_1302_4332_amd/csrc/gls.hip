@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "gemm_f64.hpp"
+#include "gemm_f64_dma.hpp"
 #include "gls.h"
 #include "adjoint_kernels.hpp"
 #include "gls_internal.hpp"
@@ -166,6 +167,13 @@ static void gemm_map(bool ta, bool tb, const GemmArgs& g, hipStream_t s) {
 }
 
 void gemm(bool ta, bool tb, bool xcd_map, const GemmArgs& g, hipStream_t s) {
+  if (!ta && !tb && xcd_map && trmm_dma_ok(g)) {
+    GemmArgs d = g;
+    const int Mt = (g.M + DB_BM - 1) / DB_BM, Nt = (g.ncols + DB_BN - 1) / DB_BN;
+    d.M = Mt * DB_BM;   // rows past mvalid are computed from A's padding and not stored
+    hipLaunchKernelGGL(trmm_f64_dma_kernel, dim3(XcdMap::grid(d, Mt, Nt)), dim3(DB_THREADS), 0, s, d);
+    return;
+  }
   const bool vec = gemm_vec_ok(g, ta, tb);
   if (xcd_map) {
     if (vec) gemm_map<MAP_XCD, true>(ta, tb, g, s);
