@@ -22,14 +22,19 @@ namespace gls {
 // are conflict-free: in A's k-column kc, chunk c (rows 2c, 2c + 1) sits in
 // slot c ^ 8 (kc & 1); in B's column j, chunk c (k = 2c, 2c + 1) sits in slot
 // c ^ (j & 7).  Two stages (48 KB) were measured best at n = 10,000 (three:
-// 3% slower, four: 15% slower; XCD groups other than 1 x 16 slower still).
+// 3% slower, four: 15% slower; XCD groups other than 1 x 16 slower still); a
+// 64 x 64 tile with four waves (two k-columns of A per load instruction) runs
+// within 0.3% of this one.
 constexpr int DB_BM = 128, DB_BN = 64, DB_BK = 16, DB_THREADS = 512, DB_STAGES = 2;
 
 __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
   constexpr int BM = DB_BM, BN = DB_BN, BK = DB_BK, NS = DB_STAGES, NW = DB_THREADS / 64;
+  constexpr int WGM = BM / 64, WGN = NW / WGM;   // waves along rows (64 each) and columns (16 each)
   constexpr int ASZ = BM * BK * 8, BSZ = BN * BK * 8, STAGE = ASZ + BSZ;
+  constexpr int AINS = ASZ / 1024;               // load instructions of A per stage (1024 / (8 BM) k-columns each)
+  constexpr int KPI = BK / AINS;
   constexpr int NLD = (ASZ + BSZ) / 1024 / NW;   // load instructions per wave and stage
-  static_assert(NLD * NW * 1024 == STAGE && BM == 128 && BN == 64 && BK == 16 && NW == 8, "tile split");
+  static_assert(NLD * NW * 1024 == STAGE && (BM == 128 || BM == 64) && BN == 16 * WGN && BK == 16, "tile split");
   __shared__ __align__(1024) char smem[NS * STAGE];
 
   int ti, tj;
@@ -40,7 +45,7 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
   if (g.a_tri == TRI_LOWER) khi = imin(khi, i0 + BM + g.a_diag);
   const int nk = (khi + BK - 1) / BK;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WGM, wn = wave / WGM;
 
   // loader: this wave issues instructions wave, wave + 8, wave + 16 of a stage
   // (0..15: A's k-columns, 16..23: B's column groups of eight)
@@ -49,16 +54,18 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
 #pragma unroll
   for (int q = 0; q < NLD; ++q) {
     const int ins = q * NW + wave;
-    if (ins < BK) {
-      const int c = lane ^ ((ins & 1) << 3);
-      src[q] = reinterpret_cast<const char*>(g.A + (int64_t)(i0 + 2 * c) + (int64_t)ins * g.lda);
+    if (ins < AINS) {
+      // k-columns KPI ins .. KPI ins + KPI - 1, BM / 2 chunks (two rows each) per column
+      const int kc = KPI * ins + lane / (BM / 2), slot = lane % (BM / 2);
+      const int c = slot ^ ((kc & 1) << 3);
+      src[q] = reinterpret_cast<const char*>(g.A + (int64_t)(i0 + 2 * c) + (int64_t)kc * g.lda);
       dst[q] = ins * 1024;
     } else {
-      const int jl = 8 * (ins - BK) + (lane >> 3);
+      const int jl = 8 * (ins - AINS) + (lane >> 3);
       const int c = (lane & 7) ^ (jl & 7);
       const int j = imin(j0 + jl, g.ncols - 1);   // columns past the end: any valid one, dropped
       src[q] = reinterpret_cast<const char*>(g.B + (int64_t)(2 * c) + (int64_t)j * g.ldb);
-      dst[q] = ASZ + (ins - BK) * 1024;
+      dst[q] = ASZ + (ins - AINS) * 1024;
     }
   }
   const uint32_t lds0 = lds_address(smem);
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
     for (int q = 0; q < NLD; ++q) {
       const int ins = q * NW + wave;
       // A advances kt columns (kt * lda doubles), B kt rows
-      const int64_t step = (ins < BK) ? (int64_t)kt * g.lda * 8 : (int64_t)kt * 8;
+      const int64_t step = (ins < AINS) ? (int64_t)kt * g.lda * 8 : (int64_t)kt * 8;
       lds_load16(src[q] + step, __builtin_amdgcn_readfirstlane(base + dst[q]));
     }
   };
@@ -88,7 +95,7 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int i = wm * 64 + a * 16 + (lane & 15);
-      offa[s][a] = kr * 1024 + (((i >> 1) ^ ((kr & 1) << 3)) << 4) + ((i & 1) << 3);
+      offa[s][a] = kr * (8 * BM) + (((i >> 1) ^ ((kr & 1) << 3)) << 4) + ((i & 1) << 3);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
