@@ -29,12 +29,13 @@ constexpr int DB_BM = 128, DB_BN = 64, DB_BK = 16, DB_THREADS = 512, DB_STAGES =
 
 __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
   constexpr int BM = DB_BM, BN = DB_BN, BK = DB_BK, NS = DB_STAGES, NW = DB_THREADS / 64;
-  constexpr int WGM = BM / 64, WGN = NW / WGM;   // waves along rows (64 each) and columns (16 each)
+  constexpr int WGM = BM / 64, WGN = NW / WGM;   // waves along rows (64 each) and columns
+  constexpr int WTN = BN / WGN, FC = WTN / 4;    // columns per wave, 4-column accumulator slices per wave
   constexpr int ASZ = BM * BK * 8, BSZ = BN * BK * 8, STAGE = ASZ + BSZ;
   constexpr int AINS = ASZ / 1024;               // load instructions of A per stage (1024 / (8 BM) k-columns each)
   constexpr int KPI = BK / AINS;
   constexpr int NLD = (ASZ + BSZ) / 1024 / NW;   // load instructions per wave and stage
-  static_assert(NLD * NW * 1024 == STAGE && (BM == 128 || BM == 64) && BN == 16 * WGN && BK == 16, "tile split");
+  static_assert(NLD * NW * 1024 == STAGE && (BM == 128 || BM == 64) && (FC == 4 || FC == 8) && BK == 16, "tile split");
   __shared__ __align__(1024) char smem[NS * STAGE];
 
   int ti, tj;
@@ -81,14 +82,14 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
     }
   };
 
-  double acc[4][4];
+  double acc[4][FC];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    for (int c = 0; c < FC; ++c) acc[a][c] = 0.0;
 
   // fragment offsets for the four k sub-steps kk = 0, 4, 8, 12: lane k row kr = kk + lane / 16
-  int offa[4][4], offb[4][4];
+  int offa[4][4], offb[4][FC];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int kr = 4 * s + (lane >> 4);
@@ -98,8 +99,8 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
       offa[s][a] = kr * (8 * BM) + (((i >> 1) ^ ((kr & 1) << 3)) << 4) + ((i & 1) << 3);
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = wn * 16 + c * 4 + (lane & 3);
+    for (int c = 0; c < FC; ++c) {
+      const int j = wn * WTN + c * 4 + (lane & 3);
       offb[s][c] = ASZ + j * 128 + (((kr >> 1) ^ (j & 7)) << 4) + ((kr & 1) << 3);
     }
   }
@@ -113,13 +114,13 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
     const char* st = smem + (it % NS) * STAGE;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      double af[4], bf[4];
+      double af[4], bf[FC];
 #pragma unroll
       for (int a = 0; a < 4; ++a) af[a] = *reinterpret_cast<const double*>(st + offa[s][a]);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) bf[c] = *reinterpret_cast<const double*>(st + offb[s][c]);
+      for (int c = 0; c < FC; ++c) bf[c] = *reinterpret_cast<const double*>(st + offb[s][c]);
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < FC; ++c)
 #pragma unroll
         for (int a = 0; a < 4; ++a) acc[a][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf[c], acc[a][c], 0, 0, 0);
     }
@@ -131,8 +132,8 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
     const int i = i0 + wm * 64 + a * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
     if (i >= g.mvalid) continue;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = j0 + wn * 16 + c * 4 + (lane & 3);
+    for (int c = 0; c < FC; ++c) {
+      const int j = j0 + wn * WTN + c * 4 + (lane & 3);
       if (j >= g.ncols) continue;
       double val = g.alpha * acc[a][c];
       if (g.beta != 0.0) val += g.beta * g.Cin[(int64_t)i + (int64_t)j * g.ldcin];
