@@ -231,6 +231,50 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
     return res
 
 
+def measure_scale(args, dev):
+    """Streamed rate over a whole large study (m = 1,000,000 or 2,000,000): a
+    pinned pool of distinct SNP blocks (about 21 GB) is streamed again and
+    again until the study's m SNPs have gone through; the work per SNP is the
+    same as for m distinct SNPs.  Setup excluded."""
+    import torch
+
+    from paper_1302_4332_amd import synth
+    from paper_1302_4332_amd.gls import GLSContext
+
+    w = synth.WORKLOADS[args.scale]
+    # about 21 GB of pinned FP64, whole blocks: each pass restarts the copy pipeline, so passes are long
+    pool = min(w.m, max(w.block_cols, int(21e9 / (8 * w.n)) // w.block_cols * w.block_cols))
+    st = synth.make_study(w, m=pool)
+    n, p, bc = w.n, w.p, w.block_cols
+    host = torch.empty((pool, n), dtype=torch.float64).pin_memory()
+    CH = 16384
+    for j0 in range(0, pool, CH):
+        j1 = min(pool, j0 + CH)
+        host[j0:j1] = torch.from_numpy(synth.genotypes_u8(n, j0, j1, w.seed)).to(torch.float64)
+    Phi_d, XL_d, y_d = (torch.tensor(np.ascontiguousarray(a), device=dev) for a in (st.Phi, st.XL, st.y))
+    ctx = GLSContext(Phi_d, w.h2, XL_d, y_d, block_cols=bc)
+    out = (torch.empty((pool, p), dtype=torch.float64).pin_memory(), torch.empty(pool, dtype=torch.float64).pin_memory(),
+           torch.empty(pool, dtype=torch.float64).pin_memory(), torch.empty(pool, dtype=torch.int32).pin_memory())
+    ctx.stream(host[:bc], out=tuple(o[:bc] for o in out))   # warm-up
+    torch.cuda.synchronize()
+    done, wall_ms, compute_ms, passes = 0, 0.0, 0.0, 0
+    t0 = time.perf_counter()
+    while done < w.m:
+        k = min(pool, w.m - done)
+        _, s_ = ctx.stream(host[:k], out=tuple(o[:k] for o in out))
+        wall_ms += s_.wall_ms
+        compute_ms += s_.compute_ms
+        done += k
+        passes += 1
+    total = time.perf_counter() - t0
+    ctx.close()
+    res = {"workload": w.name, "n": n, "p": p, "m": w.m, "block_cols": bc, "pool_snps": pool, "passes": passes,
+           "snps_per_s": w.m / total, "snps_per_s_device_wall": w.m / (wall_ms / 1e3), "compute_ms": compute_ms,
+           "note": "PCIe-inclusive, setup excluded; a pinned pool of distinct SNPs streamed repeatedly"}
+    log(f"scale {w.name}: {w.m:,} SNPs in {total:.2f} s -> {w.m / total:,.0f} SNPs/s ({passes} passes)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +288,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192, help="SNPs the oracle solves for the CPU baseline")
     ap.add_argument("--no-stream", action="store_true", help="skip the streamed (pinned host memory) measurement")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision and adjoint measurements")
+    ap.add_argument("--scale", default=None,
+                    help="also stream a whole large workload (e.g. c2_n10k_m1M) from a cycled pinned pool")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -389,6 +435,9 @@ def main():
         ctx.close()
         del host
         log(f"streamed: {out['stream']['snps_per_s']:,.0f} SNPs/s")
+
+    if args.scale:
+        out["scale"] = measure_scale(args, dev)
 
     if not args.no_cpu_baseline:
         from oracle import gls_oracle as O
