@@ -165,14 +165,56 @@ void snp_adjoint_kernel(const double* __restrict__ Xt, int64_t ldx, int N, int m
   ct[t] = kappa;
 }
 
-// acc[t] += sum over SNPs j < mb of contrib[t + j * nc] (one workgroup, fixed order).
+// acc[t] += sum over SNPs j < mb of contrib[t + j * nc]; workgroup t, each
+// thread a strided share of the SNPs, then a fixed-order tree (deterministic).
 __global__ __launch_bounds__(256) void reduce_contrib_kernel(const double* __restrict__ contrib, int nc, int mb,
                                                              double* __restrict__ acc) {
-  for (int t = threadIdx.x; t < nc; t += blockDim.x) {
-    double s = 0.0;
-    for (int j = 0; j < mb; ++j) s += contrib[t + (int64_t)j * nc];
-    acc[t] += s;
+  __shared__ double red[256];
+  const int t = blockIdx.x;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < mb; j += 256) s += contrib[t + (int64_t)j * nc];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) acc[t] += red[0];
+}
+
+// Partial sums of Wbar += X~ Cbar^T (N x P; X~ N x mb, ld N; Cbar P x mb):
+//   part[(q * P + t) * N + r] = sum over SNPs j in chunk q of X~[r, j] Cbar[t, j].
+// Thread r of workgroup (row block, chunk q); rows are coalesced, Cbar is
+// broadcast.  wbar_add_kernel then adds the `chunks` chunks in order.
+template <int P>
+__global__ __launch_bounds__(256) void wbar_partial_kernel(const double* __restrict__ Xt, int N, int mb, int chunks,
+                                                           const double* __restrict__ Cbar,
+                                                           double* __restrict__ part) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int q = blockIdx.y;
+  if (r >= N) return;
+  const int per = (mb + chunks - 1) / chunks;
+  const int j0 = q * per, j1 = min(mb, j0 + per);
+  double s[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) s[t] = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double x = Xt[r + (int64_t)j * N];
+#pragma unroll
+    for (int t = 0; t < P; ++t) s[t] += x * Cbar[t + (int64_t)j * P];
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) part[((int64_t)q * P + t) * N + r] = s[t];
+}
+
+// Wbar[r + t N] += sum over chunks q, in order, of part[(q * P + t) * N + r].
+__global__ void wbar_add_kernel(const double* __restrict__ part, int N, int P, int chunks, double* __restrict__ Wbar) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * P) return;
+  const int r = (int)(idx % N), t = (int)(idx / N);
+  double s = 0.0;
+  for (int q = 0; q < chunks; ++q) s += part[((int64_t)q * P + t) * N + r];
+  Wbar[idx] += s;
 }
 
 // Xtbar[r, j] = sum_t W[r, t] Cbar[t, j] + ebar[j] Xt[r, j]   (N x mb, ld N)

@@ -743,7 +743,7 @@ static void adjoint_snp_p(Ctx* c, int mb, const double* bbar, const double* s2ba
   const int grid = (mb + SNP_PER_WG - 1) / SNP_PER_WG;
   hipLaunchKernelGGL(snp_adjoint_kernel<P>, dim3(grid), dim3(64 * SNP_WAVES), 0, s, c->Xt, (int64_t)c->N, (int)c->N,
                      mb, c->W, c->small, (int)c->n, bbar, (int64_t)P, s2bar, vbar, c->Cb, c->eb, c->ct);
-  hipLaunchKernelGGL(reduce_contrib_kernel, dim3(1), dim3(256), 0, s, c->ct, adj_nc(P), mb, c->acc);
+  hipLaunchKernelGGL(reduce_contrib_kernel, dim3(adj_nc(P)), dim3(256), 0, s, c->ct, adj_nc(P), mb, c->acc);
   hipLaunchKernelGGL(xtbar_kernel<P>, dim3(grid_for(c->N * mb)), dim3(256), 0, s, c->W, c->Xt, c->Cb, c->eb,
                      (int)c->N, mb, c->Xtb);
 }
@@ -784,10 +784,15 @@ gls_status block_backward(Ctx* c, int mb, const double* XR, int64_t ld_xr, const
 #define GLS_ADJ(P) adjoint_snp_p<P>(c, mb, bbar, s2bar, vbar, s)
   GLS_P_SWITCH(c->p, GLS_ADJ)
 #undef GLS_ADJ
-  {  // Wbar += X~_R Cbar^T   (op(B)[k][j] = Cbar[j + k p])
-    GemmArgs g = gemm_args(c->Xt, N, c->Cb, c->p, c->Wb, N, (int)N, c->p, mb, 1.0);
-    g.beta = 1.0;
-    gemm(false, true, false, g, s);
+  {  // Wbar += X~_R Cbar^T: partial sums over SNP chunks into Xb (free until the next product), then in order
+    const int p = c->p;
+    const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(32, c->plan.bcp / p));
+#define GLS_WP(P)                                                                                                 \
+  hipLaunchKernelGGL(wbar_partial_kernel<P>, dim3((unsigned)((N + 255) / 256), (unsigned)chunks), dim3(256), 0, s, \
+                     c->Xt, (int)N, mb, chunks, c->Cb, c->Xb);
+    GLS_P_SWITCH(p, GLS_WP)
+#undef GLS_WP
+    hipLaunchKernelGGL(wbar_add_kernel, dim3(grid_for(N * p)), dim3(256), 0, s, c->Xb, (int)N, p, chunks, c->Wb);
   }
   {  // X_R bar = L^-T X~_R bar   (op(A) = (L^-1)^T, upper: non-zero for k >= i)
     GemmArgs g = gemm_args(c->Linv, N, c->Xtb, N, c->Xb, N, (int)N, mb, (int)N, 1.0);
