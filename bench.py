@@ -152,11 +152,13 @@ def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
 def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
     """Genotype bytes: the int8-slice product (FP64-accurate) with the SNP
     matrix resident in HBM, and the streamed rates from pinned host memory
-    and from a file (1 byte per sample instead of 8)."""
+    and from a file, as bytes (1 byte per sample instead of 8) and as packed
+    2-bit dosages (a quarter byte per sample)."""
     import tempfile
 
     import torch
 
+    from paper_1302_4332_amd import synth
     from paper_1302_4332_amd.gls import GLSContext
 
     w = st.w
@@ -201,33 +203,38 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
     G_h = torch.empty((m, n), dtype=torch.uint8).pin_memory()
     G_h.copy_(G_d)
     del G_d
-    for prec in ("fp64", "int8_emu"):
-        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec)
-        ctx.stream(G_h)
-        (_, _, _, _), ss = ctx.stream(G_h)
-        res[f"stream_u8_{prec}"] = {"snps_per_s": m / (ss.wall_ms / 1e3), "wall_ms": ss.wall_ms,
-                                    "compute_ms": ss.compute_ms, "h2d_GBps": ss.h2d_bytes / (ss.wall_ms / 1e3) / 1e9}
-        log(f"stream bytes {prec}: {m / (ss.wall_ms / 1e3):,.0f} SNPs/s")
-        ctx.close()
-    # from storage: the byte matrix written to a file, then streamed through
-    # the reader thread and three host buffers; page cache dropped for the file
-    with tempfile.TemporaryDirectory(dir=os.environ.get("TMPDIR", "/tmp")) as d:
-        path = os.path.join(d, "snps.u8")
-        G_h.numpy().tofile(path)
+    G2_h = torch.from_numpy(synth.pack_dosages_2bit(G_h.numpy())).pin_memory()
+    inputs = {"u8": (G_h, False), "u2": (G2_h, True)}
+    for fmt, (H, packed) in inputs.items():
         for prec in ("fp64", "int8_emu"):
             ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec)
-            fd = os.open(path, os.O_RDONLY)
-            os.fsync(fd) if hasattr(os, "fsync") else None
-            os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
-            os.close(fd)
-            (_, _, _, _), fs = ctx.stream_file(path, m, torch.uint8)
-            res[f"stream_file_u8_{prec}"] = {"snps_per_s": m / (fs.wall_ms / 1e3), "wall_ms": fs.wall_ms,
-                                             "read_ms": fs.read_ms, "file_GBps": fs.file_bytes / (fs.read_ms / 1e3) / 1e9
-                                             if fs.read_ms else None, "compute_ms": fs.compute_ms,
-                                             "note": "page cache of the file dropped before the run"}
-            log(f"stream file bytes {prec}: {m / (fs.wall_ms / 1e3):,.0f} SNPs/s (read {fs.read_ms:.0f} ms)")
+            ctx.stream(H, packed=packed)
+            (_, _, _, _), ss = ctx.stream(H, packed=packed)
+            res[f"stream_{fmt}_{prec}"] = {"snps_per_s": m / (ss.wall_ms / 1e3), "wall_ms": ss.wall_ms,
+                                           "compute_ms": ss.compute_ms,
+                                           "h2d_GBps": ss.h2d_bytes / (ss.wall_ms / 1e3) / 1e9}
+            log(f"stream {fmt} {prec}: {m / (ss.wall_ms / 1e3):,.0f} SNPs/s")
             ctx.close()
-    del G_h
+    # from storage: the dosages written to a file, then streamed through the
+    # reader thread and three host buffers; page cache dropped for the file
+    with tempfile.TemporaryDirectory(dir=os.environ.get("TMPDIR", "/tmp")) as d:
+        for fmt, (H, _) in inputs.items():
+            path = os.path.join(d, f"snps.{fmt}")
+            H.numpy().tofile(path)
+            for prec in ("fp64", "int8_emu"):
+                ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec)
+                fd = os.open(path, os.O_RDONLY)
+                os.fsync(fd)
+                os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+                os.close(fd)
+                (_, _, _, _), fs = ctx.stream_file(path, m, torch.uint8 if fmt == "u8" else "u2")
+                res[f"stream_file_{fmt}_{prec}"] = {
+                    "snps_per_s": m / (fs.wall_ms / 1e3), "wall_ms": fs.wall_ms, "read_ms": fs.read_ms,
+                    "file_GBps": fs.file_bytes / (fs.read_ms / 1e3) / 1e9 if fs.read_ms else None,
+                    "compute_ms": fs.compute_ms, "note": "page cache of the file dropped before the run"}
+                log(f"stream file {fmt} {prec}: {m / (fs.wall_ms / 1e3):,.0f} SNPs/s (read {fs.read_ms:.0f} ms)")
+                ctx.close()
+    del G_h, G2_h
     return res
 
 
@@ -288,6 +295,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192, help="SNPs the oracle solves for the CPU baseline")
     ap.add_argument("--no-stream", action="store_true", help="skip the streamed (pinned host memory) measurement")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision and adjoint measurements")
+    ap.add_argument("--no-bytes", action="store_true", help="skip the genotype-byte and packed-dosage measurements")
     ap.add_argument("--scale", default=None,
                     help="also stream a whole large workload (e.g. c2_n10k_m1M) from a cycled pinned pool")
     ap.add_argument("--calib-copy", action="store_true",
@@ -414,7 +422,7 @@ def main():
 
     if not args.no_forms:
         out["forms"] = measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev)
-    if not args.no_forms:
+    if not args.no_bytes:
         out["bytes"] = measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_h)
     if not args.no_stream:
         host = torch.empty((m, n), dtype=torch.float64).pin_memory()

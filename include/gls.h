@@ -64,7 +64,7 @@ typedef enum {
   GLS_FP32_IR = 1,  /* FP32 MFMA bulk + FP64 residual refinement sweeps          */
   GLS_FP16_IR = 2,  /* FP16 MFMA (power-of-two column scaling) + FP64 refinement */
   GLS_BF16_IR = 3,  /* BF16 MFMA (power-of-two column scaling) + FP64 refinement */
-  GLS_INT8_EMU = 4  /* byte dosages only (gls_block_u8 / gls_stream_u8): the product
+  GLS_INT8_EMU = 4  /* dosage input only (the _u8 and _u2 entry points): the product
                        with L^-1 as eight exact int8 slice products on the integer
                        matrix cores, combined in FP64 (FP64-level accuracy); FP64
                        input on such a handle runs the plain FP64 product        */
@@ -130,6 +130,18 @@ gls_status gls_block_u8(gls_handle h, int32_t mb, const uint8_t* G, int64_t ld_g
                         double* b, int64_t ld_b, double* sigma2, double* v,
                         int32_t* snp_status, void* stream);
 
+/* One SNP block given as packed 2-bit dosages: column j occupies bytes
+ * [j * ld_g2, j * ld_g2 + ceil(n / 4)) of G2 (ld_g2 >= ceil(n / 4)); sample k's
+ * dosage is the 2-bit code in bits [2 (k % 4), 2 (k % 4) + 2) of the column's
+ * byte k / 4, read as the integer 0..3 (no missing-value code).  Bits of a
+ * column's last byte past sample n - 1 are ignored.  The codes are expanded
+ * on the device, and the results are bitwise those of gls_block_u8 on the same
+ * dosages as bytes (every precision).  Moves a quarter byte per sample.  Same
+ * outputs, errors and asynchrony as gls_block. */
+gls_status gls_block_u2(gls_handle h, int32_t mb, const uint8_t* G2, int64_t ld_g2,
+                        double* b, int64_t ld_b, double* sigma2, double* v,
+                        int32_t* snp_status, void* stream);
+
 /* Per-stream timing and byte counts filled by gls_stream (may be NULL). */
 typedef struct {
   int64_t blocks;        /* blocks processed                                  */
@@ -168,10 +180,21 @@ gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0,
                          int32_t* status_host, void* compute_stream, void* copy_stream,
                          gls_stream_stats* stats_out);
 
+/* gls_stream for packed 2-bit dosages: G2_host holds m columns of
+ * ceil(n / 4) bytes at stride ld_g2 (>= ceil(n / 4)) bytes, in page-locked host
+ * memory, in the layout of gls_block_u2; blocks are processed as by
+ * gls_block_u2. */
+gls_status gls_stream_u2(gls_handle h, int64_t m, int64_t col0,
+                         const uint8_t* G2_host, int64_t ld_g2,
+                         double* b_host, double* sigma2_host, double* v_host,
+                         int32_t* status_host, void* compute_stream, void* copy_stream,
+                         gls_stream_stats* stats_out);
+
 /* Streamed study read from storage (Sec. 3.1, both buffering levels): the
  * SNP matrix is a file holding SNP j's n samples contiguously at byte
- * offset + j * n * elem_bytes, as FP64 (elem_bytes 8) or genotype bytes
- * (elem_bytes 1).  A reader thread reads block b+2 into one of three
+ * offset + j * c, as FP64 (elem_bits 64, c = 8 n), genotype bytes (elem_bits 8,
+ * c = n) or packed 2-bit dosages in the layout of gls_block_u2 (elem_bits 2,
+ * c = ceil(n / 4)).  A reader thread reads block b+2 into one of three
  * page-locked host buffers while block b+1 waits in another and block b is
  * copied to the device (two device buffers alternate as in gls_stream); a
  * host buffer is reused only once its copy has completed.  host_ws is the
@@ -180,8 +203,8 @@ gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0,
  * (unopenable file) or GLS_ERR_STATE (short read), with gls_last_error().
  * With GLS_STREAM_SERIAL the calling thread reads, copies and solves one
  * block after another (no overlap at either level). */
-size_t gls_stream_file_host_bytes(gls_handle h, int32_t elem_bytes);
-gls_status gls_stream_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bytes,
+size_t gls_stream_file_host_bytes(gls_handle h, int32_t elem_bits);
+gls_status gls_stream_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bits,
                            int64_t m, int64_t col0, void* host_ws, size_t host_ws_bytes,
                            double* b_host, double* sigma2_host, double* v_host,
                            int32_t* status_host, void* compute_stream, void* copy_stream,

@@ -531,6 +531,25 @@ gls_status gls_block_u8(gls_handle h, int32_t mb, const uint8_t* G, int64_t ld_g
   return GLS_OK;
 }
 
+gls_status gls_block_u2(gls_handle h, int32_t mb, const uint8_t* G2, int64_t ld_g2, double* b, int64_t ld_b,
+                        double* sigma2, double* v, int32_t* snp_status, void* stream) {
+  Ctx* c = h;
+  if (!c || !c->ready) {
+    set_err("gls_block_u2: handle is not set up");
+    return GLS_ERR_STATE;
+  }
+  if (mb < 0 || mb > c->bc) return arg_fail("gls_block_u2: mb must lie in [0, block_cols]");
+  if (mb == 0) return GLS_OK;
+  if (!G2 || ld_g2 < (c->n + 3) / 4) return arg_fail("gls_block_u2: G2 is NULL or ld_g2 < ceil(n / 4)");
+  if (!b || ld_b < c->p || !sigma2 || !v || !snp_status) return arg_fail("gls_block_u2: NULL output or ld_b < p");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gls_status st = block_forward_u2(c, mb, G2, ld_g2, b, ld_b, sigma2, v, snp_status, s);
+  if (st != GLS_OK) return st;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "gls_block_u2: launch");
+  return GLS_OK;
+}
+
 void gls_destroy(gls_handle h) {
   Ctx* c = h;
   if (!c) return;
@@ -699,13 +718,13 @@ namespace gls {
 // per group (measured best of 1x16 .. 16x1 at n = 10,000, 8,192 SNPs).
 constexpr int OZ_MAP_GM = 4, OZ_MAP_GN = 4;
 
-gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, double* b, int64_t ld_b, double* s2,
-                            double* v, int* st, hipStream_t s) {
+// The block's dosages are in c->ubp (N x mb bytes, rows >= n zero): the
+// product on the integer matrix cores, then the per-SNP work.
+static void block_forward_i8(Ctx* c, int mb, double* b, int64_t ld_b, double* s2, double* v, int* st, hipStream_t s) {
   const int64_t N = c->N;
-  if (c->opts.precision == GLS_INT8_EMU) {
+  {
     {
       PhaseTimer t(c, PH_WHITEN, s);
-      hipLaunchKernelGGL(pack_u8_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->ubp);
       OzArgs a;
       a.A = c->sl;
       a.ex = c->ex;
@@ -724,9 +743,38 @@ gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, doubl
     }
     PhaseTimer t(c, PH_SNP, s);
     snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
+  }
+}
+
+gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, double* b, int64_t ld_b, double* s2,
+                            double* v, int* st, hipStream_t s) {
+  const int64_t N = c->N;
+  if (c->opts.precision == GLS_INT8_EMU) {
+    {
+      PhaseTimer t(c, PH_WHITEN, s);
+      hipLaunchKernelGGL(pack_u8_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->ubp);
+    }
+    block_forward_i8(c, mb, b, ld_b, s2, v, st, s);
     return GLS_OK;
   }
   hipLaunchKernelGGL(u8_to_f64_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->x64);
+  return block_forward(c, mb, c->x64, N, b, ld_b, s2, v, st, s);
+}
+
+gls_status block_forward_u2(Ctx* c, int mb, const uint8_t* G2, int64_t ldg, double* b, int64_t ld_b, double* s2,
+                            double* v, int* st, hipStream_t s) {
+  const int64_t N = c->N;
+  if (c->opts.precision == GLS_INT8_EMU) {
+    {
+      PhaseTimer t(c, PH_WHITEN, s);
+      hipLaunchKernelGGL(unpack_u2_kernel, dim3(grid_for(N / 4 * mb)), dim3(256), 0, s, G2, ldg, (int)c->n, (int)N,
+                         mb, reinterpret_cast<uint32_t*>(c->ubp));
+    }
+    block_forward_i8(c, mb, b, ld_b, s2, v, st, s);
+    return GLS_OK;
+  }
+  hipLaunchKernelGGL(unpack_u2_f64_kernel, dim3(grid_for(N / 4 * mb)), dim3(256), 0, s, G2, ldg, (int)c->n, (int)N,
+                     mb, c->x64);
   return block_forward(c, mb, c->x64, N, b, ld_b, s2, v, st, s);
 }
 

@@ -84,6 +84,47 @@ __global__ void u8_to_f64_kernel(const uint8_t* __restrict__ G, int64_t ldg, int
   }
 }
 
+// Packed dosages: four 2-bit codes per byte, sample k of a column in bits
+// [2 (k % 4), 2 (k % 4) + 2) of the column's byte k / 4; code value = dosage
+// (0..3).  Bits of the last byte past row n - 1 are ignored.  One thread per
+// four output rows; rows n..N-1 are zero.
+__device__ __forceinline__ uint32_t unpack_quad(const uint8_t* __restrict__ G2, int64_t ldg, int n, int q, int j) {
+  const int k0 = 4 * q;
+  if (k0 >= n) return 0u;
+  const uint32_t b = G2[(int64_t)j * ldg + q];
+  uint32_t w = (b & 3u) | ((b & 0x0cu) << 6) | ((b & 0x30u) << 12) | ((b & 0xc0u) << 18);
+  const int rem = n - k0;
+  if (rem < 4) w &= (1u << (8 * rem)) - 1u;
+  return w;   // byte t = dosage of row k0 + t
+}
+
+// Packed dosages of a block into an N-row, zero-padded column-major byte buffer.
+__global__ void unpack_u2_kernel(const uint8_t* __restrict__ G2, int64_t ldg, int n, int N, int mb,
+                                 uint32_t* __restrict__ out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int Q = N / 4;
+  const int64_t total = (int64_t)Q * mb;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % Q), j = (int)(idx / Q);
+    out[idx] = unpack_quad(G2, ldg, n, q, j);
+  }
+}
+
+// Packed dosages of a block as FP64 (exact), N-row zero-padded, ld N.
+__global__ void unpack_u2_f64_kernel(const uint8_t* __restrict__ G2, int64_t ldg, int n, int N, int mb,
+                                     double* __restrict__ out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int Q = N / 4;
+  const int64_t total = (int64_t)Q * mb;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % Q), j = (int)(idx / Q);
+    const uint32_t w = unpack_quad(G2, ldg, n, q, j);
+    double2* o = reinterpret_cast<double2*>(out + (int64_t)j * N + 4 * q);
+    o[0] = double2{(double)(w & 0xffu), (double)((w >> 8) & 0xffu)};
+    o[1] = double2{(double)((w >> 16) & 0xffu), (double)(w >> 24)};
+  }
+}
+
 struct OzArgs {
   const int8_t* A;        // OZ_SLICES planes of N x N, row-major
   const int* ex;          // row exponents

@@ -42,14 +42,29 @@ struct EventPool {
   }
 };
 
+// Element of a packed-dosage column: one byte holding four samples' 2-bit
+// codes.  A distinct type so that the stream templates pick the right
+// staging buffer and block solver.
+struct Packed2 {
+  uint8_t bits;
+};
+
+// Elements per column of the SNP matrix in each input format.
+int64_t col_elems(const Ctx* c, const double*) { return c->n; }
+int64_t col_elems(const Ctx* c, const uint8_t*) { return c->n; }
+int64_t col_elems(const Ctx* c, const Packed2*) { return (c->n + 3) / 4; }
+
+// rows: elements per column (dense in dst)
 template <typename T>
-hipError_t h2d_block(T* dst, int64_t n, const T* src, int64_t ld, int64_t cols, hipStream_t s) {
-  if (ld == n) return hipMemcpyAsync(dst, src, sizeof(T) * n * cols, hipMemcpyHostToDevice, s);
-  return hipMemcpy2DAsync(dst, sizeof(T) * n, src, sizeof(T) * ld, sizeof(T) * n, cols, hipMemcpyHostToDevice, s);
+hipError_t h2d_block(T* dst, int64_t rows, const T* src, int64_t ld, int64_t cols, hipStream_t s) {
+  if (ld == rows) return hipMemcpyAsync(dst, src, sizeof(T) * rows * cols, hipMemcpyHostToDevice, s);
+  return hipMemcpy2DAsync(dst, sizeof(T) * rows, src, sizeof(T) * ld, sizeof(T) * rows, cols, hipMemcpyHostToDevice,
+                          s);
 }
 
 double* stage(Ctx* c, int i, const double*) { return c->buf[i]; }
 uint8_t* stage(Ctx* c, int i, const uint8_t*) { return c->ub[i]; }
+Packed2* stage(Ctx* c, int i, const Packed2*) { return reinterpret_cast<Packed2*>(c->ub[i]); }
 
 gls_status solve_block(Ctx* c, int mb, const double* X, int64_t ld, double* b, int64_t ldb, double* s2, double* v,
                        int* st, hipStream_t s) {
@@ -58,6 +73,10 @@ gls_status solve_block(Ctx* c, int mb, const double* X, int64_t ld, double* b, i
 gls_status solve_block(Ctx* c, int mb, const uint8_t* X, int64_t ld, double* b, int64_t ldb, double* s2, double* v,
                        int* st, hipStream_t s) {
   return block_forward_u8(c, mb, X, ld, b, ldb, s2, v, st, s);
+}
+gls_status solve_block(Ctx* c, int mb, const Packed2* X, int64_t ld, double* b, int64_t ldb, double* s2, double* v,
+                       int* st, hipStream_t s) {
+  return block_forward_u2(c, mb, reinterpret_cast<const uint8_t*>(X), ld, b, ldb, s2, v, st, s);
 }
 
 }  // namespace
@@ -69,12 +88,13 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
   Ctx* c = h;
   if (!c || !c->ready) return arg_fail("gls_stream: handle is not set up"), GLS_ERR_STATE;
   if (m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream: need 0 <= col0 <= m");
-  if (!XR_host || ld_xr < c->n) return arg_fail("gls_stream: XR_host is NULL or ld_xr < n");
+  const int64_t rows = col_elems(c, XR_host);
+  if (!XR_host || ld_xr < rows) return arg_fail("gls_stream: the SNP matrix is NULL or its ld is below a column");
   if (!b_host || !sigma2_host || !v_host || !status_host) return arg_fail("gls_stream: NULL host output");
   hipStream_t sc = static_cast<hipStream_t>(compute_stream);
   // serial mode: every copy on the compute stream, so nothing overlaps
   hipStream_t sx = (c->opts.flags & GLS_STREAM_SERIAL) ? sc : static_cast<hipStream_t>(copy_stream);
-  const int64_t n = c->n, bc = c->bc;
+  const int64_t bc = c->bc;
   const int p = c->p;
   // Block schedule.  Full blocks of bc, except that a stream of large blocks
   // (bc >= 2,048) starts with short ones, bc / 8 growing by a quarter per
@@ -108,10 +128,10 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
   auto src_of = [&](int64_t blk) { return XR_host + (col0 + bstart[blk]) * ld_xr; };
 
   if ((e = hipEventRecord(wall0, sx)) != hipSuccess) return hip_fail(e, "gls_stream: record");
-  if ((e = h2d_block(stage(c, 0, XR_host), n, src_of(0), ld_xr, cols_of(0), sx)) != hipSuccess)
+  if ((e = h2d_block(stage(c, 0, XR_host), rows, src_of(0), ld_xr, cols_of(0), sx)) != hipSuccess)
     return hip_fail(e, "gls_stream: H2D");
   if ((e = hipEventRecord(c->ev_copy[0], sx)) != hipSuccess) return hip_fail(e, "gls_stream: record");
-  st.h2d_bytes += sizeof(T) * n * cols_of(0);
+  st.h2d_bytes += sizeof(T) * rows * cols_of(0);
 
   for (int64_t blk = 0; blk < nblk; ++blk) {
     const int cur = (int)(blk & 1), nxt = cur ^ 1;
@@ -121,20 +141,20 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
       // beta may only be overwritten once the solve that last read it is done
       if (blk >= 1 && (e = hipStreamWaitEvent(sx, c->ev_comp[nxt], 0)) != hipSuccess)
         return hip_fail(e, "gls_stream: wait");
-      if ((e = h2d_block(stage(c, nxt, XR_host), n, src_of(blk + 1), ld_xr, cols_of(blk + 1), sx)) != hipSuccess)
+      if ((e = h2d_block(stage(c, nxt, XR_host), rows, src_of(blk + 1), ld_xr, cols_of(blk + 1), sx)) != hipSuccess)
         return hip_fail(e, "gls_stream: H2D");
       if ((e = hipEventRecord(c->ev_copy[nxt], sx)) != hipSuccess) return hip_fail(e, "gls_stream: record");
-      st.h2d_bytes += sizeof(T) * n * cols_of(blk + 1);
+      st.h2d_bytes += sizeof(T) * rows * cols_of(blk + 1);
     }
     if (sx == sc && blk >= 1) {   // serial: this block's copy only now, behind the previous results
-      if ((e = h2d_block(stage(c, cur, XR_host), n, src_of(blk), ld_xr, cols, sc)) != hipSuccess)
+      if ((e = h2d_block(stage(c, cur, XR_host), rows, src_of(blk), ld_xr, cols, sc)) != hipSuccess)
         return hip_fail(e, "gls_stream: H2D");
       if ((e = hipEventRecord(c->ev_copy[cur], sc)) != hipSuccess) return hip_fail(e, "gls_stream: record");
-      st.h2d_bytes += sizeof(T) * n * cols;
+      st.h2d_bytes += sizeof(T) * rows * cols;
     }
     if ((e = hipStreamWaitEvent(sc, c->ev_copy[cur], 0)) != hipSuccess) return hip_fail(e, "gls_stream: wait");
     if ((e = hipEventRecord(pool.ev[2 * blk], sc)) != hipSuccess) return hip_fail(e, "gls_stream: record");
-    gls_status r = solve_block(c, (int)cols, stage(c, cur, XR_host), n, c->ob, p, c->os2, c->ov, c->ost, sc);
+    gls_status r = solve_block(c, (int)cols, stage(c, cur, XR_host), rows, c->ob, p, c->os2, c->ov, c->ost, sc);
     if (r != GLS_OK) return r;
     if ((e = hipEventRecord(c->ev_comp[cur], sc)) != hipSuccess) return hip_fail(e, "gls_stream: record");
     if ((e = hipEventRecord(pool.ev[2 * blk + 1], sc)) != hipSuccess) return hip_fail(e, "gls_stream: record");
@@ -188,6 +208,13 @@ extern "C" gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0, const
                      copy_stream, stats_out);
 }
 
+extern "C" gls_status gls_stream_u2(gls_handle h, int64_t m, int64_t col0, const uint8_t* G2_host, int64_t ld_g2,
+                                    double* b_host, double* sigma2_host, double* v_host, int32_t* status_host,
+                                    void* compute_stream, void* copy_stream, gls_stream_stats* stats_out) {
+  return stream_impl(h, m, col0, reinterpret_cast<const Packed2*>(G2_host), ld_g2, b_host, sigma2_host, v_host,
+                     status_host, compute_stream, copy_stream, stats_out);
+}
+
 // ---------------------------------------------------------------------------
 // Streaming from storage: reader thread -> three host buffers -> two device
 // buffers.
@@ -225,8 +252,9 @@ bool read_fully(int fd, void* dst, size_t len, off_t off, int* err) {
   return true;
 }
 
-size_t host_ring_bytes(const Ctx* c, int elem) {
-  const size_t one = (size_t)c->n * (size_t)c->bc * (size_t)elem;
+// three host buffers of one block each; col_bytes: bytes per SNP column
+size_t host_ring_bytes(const Ctx* c, int64_t col_bytes) {
+  const size_t one = (size_t)col_bytes * (size_t)c->bc;
   return 3 * ((one + 4095) / 4096 * 4096);
 }
 
@@ -234,7 +262,7 @@ template <typename T>
 gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t col0, char* host,
                             double* b_host, double* sigma2_host, double* v_host, int32_t* status_host,
                             hipStream_t sc, hipStream_t sx_in, gls_stream_stats* stats_out) {
-  const int64_t n = c->n, bc = c->bc;
+  const int64_t bc = c->bc, rows = col_elems(c, (const T*)nullptr);
   const int p = c->p;
   const bool serial = (c->opts.flags & GLS_STREAM_SERIAL) != 0;
   hipStream_t sx = serial ? sc : sx_in;
@@ -244,11 +272,11 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
     if (stats_out) *stats_out = st;
     return GLS_OK;
   }
-  const size_t slot_bytes = host_ring_bytes(c, sizeof(T)) / 3;
+  const size_t slot_bytes = host_ring_bytes(c, rows * (int64_t)sizeof(T)) / 3;
   T* hb[3];
   for (int i = 0; i < 3; ++i) hb[i] = reinterpret_cast<T*>(host + i * slot_bytes);
   auto cols_of = [&](int64_t blk) { return std::min<int64_t>(bc, m - col0 - blk * bc); };
-  auto file_off = [&](int64_t blk) { return (off_t)(offset + (col0 + blk * bc) * n * (int64_t)sizeof(T)); };
+  auto file_off = [&](int64_t blk) { return (off_t)(offset + (col0 + blk * bc) * rows * (int64_t)sizeof(T)); };
 
   EventPool pool;
   hipError_t e;
@@ -269,7 +297,7 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
           if (ring.stop) return;
           ring.free_[slot] = false;
         }
-        const size_t len = (size_t)(cols_of(blk) * n) * sizeof(T);
+        const size_t len = (size_t)(cols_of(blk) * rows) * sizeof(T);
         int err = 0;
         auto t0 = std::chrono::steady_clock::now();
         const bool ok = read_fully(fd, hb[slot], len, file_off(blk), &err);
@@ -312,7 +340,7 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
     if (serial) {
       int err = 0;
       auto t0 = std::chrono::steady_clock::now();
-      const size_t len = (size_t)(cols * n) * sizeof(T);
+      const size_t len = (size_t)(cols * rows) * sizeof(T);
       if (!read_fully(fd, hb[slot], len, file_off(blk), &err)) {
         set_last_error_str(err > 0 ? "gls_stream_file: read failed" : "gls_stream_file: file shorter than m columns");
         return fail(GLS_ERR_STATE);
@@ -332,13 +360,14 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
     // device buffer cur may be overwritten once the solve two blocks back is done
     if (!serial && blk >= 2 && (e = hipStreamWaitEvent(sx, c->ev_comp[cur], 0)) != hipSuccess)
       return fail(hip_fail(e, "gls_stream_file: wait"));
-    if ((e = h2d_block(stage(c, cur, (const T*)nullptr), n, hb[slot], n, cols, sx)) != hipSuccess)
+    if ((e = h2d_block(stage(c, cur, (const T*)nullptr), rows, hb[slot], rows, cols, sx)) != hipSuccess)
       return fail(hip_fail(e, "gls_stream_file: H2D"));
     if ((e = hipEventRecord(ev_h2d(blk), sx)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
-    st.h2d_bytes += (int64_t)sizeof(T) * n * cols;
+    st.h2d_bytes += (int64_t)sizeof(T) * rows * cols;
     if ((e = hipStreamWaitEvent(sc, ev_h2d(blk), 0)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: wait"));
     if ((e = hipEventRecord(pool.ev[2 * blk], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
-    gls_status r = solve_block(c, (int)cols, stage(c, cur, (const T*)nullptr), n, c->ob, p, c->os2, c->ov, c->ost, sc);
+    gls_status r =
+        solve_block(c, (int)cols, stage(c, cur, (const T*)nullptr), rows, c->ob, p, c->os2, c->ov, c->ost, sc);
     if (r != GLS_OK) return fail(r);
     if ((e = hipEventRecord(c->ev_comp[cur], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
     if ((e = hipEventRecord(pool.ev[2 * blk + 1], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
@@ -382,34 +411,49 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
 
 }  // namespace
 
-extern "C" size_t gls_stream_file_host_bytes(gls_handle h, int32_t elem_bytes) {
+namespace {
+// bytes per SNP column in a file of elem_bits-bit entries (64, 8 or 2); 0 if invalid
+int64_t file_col_bytes(const Ctx* c, int32_t elem_bits) {
+  switch (elem_bits) {
+    case 64: return 8 * c->n;
+    case 8: return c->n;
+    case 2: return (c->n + 3) / 4;
+    default: return 0;
+  }
+}
+}  // namespace
+
+extern "C" size_t gls_stream_file_host_bytes(gls_handle h, int32_t elem_bits) {
   const Ctx* c = h;
-  if (!c || !c->ready || (elem_bytes != 8 && elem_bytes != 1)) return 0;
-  return host_ring_bytes(c, elem_bytes);
+  if (!c || !c->ready || file_col_bytes(c, elem_bits) == 0) return 0;
+  return host_ring_bytes(c, file_col_bytes(c, elem_bits));
 }
 
-extern "C" gls_status gls_stream_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bytes, int64_t m,
+extern "C" gls_status gls_stream_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bits, int64_t m,
                                       int64_t col0, void* host_ws, size_t host_ws_bytes, double* b_host,
                                       double* sigma2_host, double* v_host, int32_t* status_host,
                                       void* compute_stream, void* copy_stream, gls_stream_stats* stats_out) {
   Ctx* c = h;
   if (!c || !c->ready) return arg_fail("gls_stream_file: handle is not set up"), GLS_ERR_STATE;
   if (!path || offset < 0 || m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream_file: bad path/offset/m/col0");
-  if (elem_bytes != 8 && elem_bytes != 1) return arg_fail("gls_stream_file: elem_bytes must be 8 or 1");
-  if (!host_ws || host_ws_bytes < host_ring_bytes(c, elem_bytes))
+  if (file_col_bytes(c, elem_bits) == 0) return arg_fail("gls_stream_file: elem_bits must be 64, 8 or 2");
+  if (!host_ws || host_ws_bytes < host_ring_bytes(c, file_col_bytes(c, elem_bits)))
     return arg_fail("gls_stream_file: host_ws smaller than gls_stream_file_host_bytes()");
   if (!b_host || !sigma2_host || !v_host || !status_host) return arg_fail("gls_stream_file: NULL host output");
   const int fd = open(path, O_RDONLY);
   if (fd < 0) return arg_fail("gls_stream_file: cannot open the file");
   gls_status st;
-  if (elem_bytes == 8)
-    st = stream_file_impl<double>(c, fd, offset, m, col0, static_cast<char*>(host_ws), b_host, sigma2_host, v_host,
-                                  status_host, static_cast<hipStream_t>(compute_stream),
-                                  static_cast<hipStream_t>(copy_stream), stats_out);
+  const hipStream_t sc = static_cast<hipStream_t>(compute_stream), sx = static_cast<hipStream_t>(copy_stream);
+  char* ring = static_cast<char*>(host_ws);
+  if (elem_bits == 64)
+    st = stream_file_impl<double>(c, fd, offset, m, col0, ring, b_host, sigma2_host, v_host, status_host, sc, sx,
+                                  stats_out);
+  else if (elem_bits == 8)
+    st = stream_file_impl<uint8_t>(c, fd, offset, m, col0, ring, b_host, sigma2_host, v_host, status_host, sc, sx,
+                                   stats_out);
   else
-    st = stream_file_impl<uint8_t>(c, fd, offset, m, col0, static_cast<char*>(host_ws), b_host, sigma2_host, v_host,
-                                   status_host, static_cast<hipStream_t>(compute_stream),
-                                   static_cast<hipStream_t>(copy_stream), stats_out);
+    st = stream_file_impl<Packed2>(c, fd, offset, m, col0, ring, b_host, sigma2_host, v_host, status_host, sc, sx,
+                                   stats_out);
   close(fd);
   return st;
 }

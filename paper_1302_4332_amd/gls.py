@@ -70,6 +70,9 @@ SIGNATURES = {
     "gls_block_u8": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _P, _P, _P]),
     "gls_stream_u8": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
                                      ctypes.POINTER(GlsStreamStats)]),
+    "gls_block_u2": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _P, _P, _P]),
+    "gls_stream_u2": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
+                                     ctypes.POINTER(GlsStreamStats)]),
     "gls_stream_file_host_bytes": (ctypes.c_size_t, [_P, _I32]),
     "gls_stream_file": (ctypes.c_int, [_P, ctypes.c_char_p, _I64, _I32, _I64, _I64, _P, ctypes.c_size_t,
                                        _P, _P, _P, _P, _P, _P, ctypes.POINTER(GlsStreamStats)]),
@@ -83,6 +86,9 @@ SIGNATURES = {
 }
 
 _lib = None
+
+# gls_stream_file's elem_bits for each file format
+_FILE_BITS = {torch.float64: 64, "f64": 64, torch.uint8: 8, "u8": 8, "u2": 2}
 
 
 def lib() -> ctypes.CDLL:
@@ -199,29 +205,43 @@ class GLSContext:
                              _ptr(b), self.p, _ptr(sigma2), _ptr(v), _ptr(status), _stream(stream))
         _check(st)
 
-    def block_u8_into(self, G, b, sigma2, v, status, stream=None):
-        """One block of genotype bytes (mb, n) uint8 CUDA into caller-provided outputs."""
+    def _dosage_block_into(self, entry, rowbytes, G, b, sigma2, v, status, stream):
         _need(G, "G", torch.uint8)
         mb = G.shape[0]
-        if G.dim() != 2 or G.shape[1] != self.n:
-            raise ValueError(f"G must have shape (mb, {self.n})")
+        if G.dim() != 2 or G.shape[1] != rowbytes:
+            raise ValueError(f"G must have shape (mb, {rowbytes})")
         for t, name, dt in ((b, "b", torch.float64), (sigma2, "sigma2", torch.float64),
                             (v, "v", torch.float64), (status, "status", torch.int32)):
             _need(t, name, dt)
             if t.shape[0] != mb or (name == "b" and tuple(t.shape) != (mb, self.p)):
                 raise ValueError(f"{name} has the wrong shape {tuple(t.shape)}")
-        _check(lib().gls_block_u8(self.handle, mb, _ptr(G), self.n, _ptr(b), self.p, _ptr(sigma2), _ptr(v),
-                                  _ptr(status), _stream(stream)))
+        _check(entry(self.handle, mb, _ptr(G), rowbytes, _ptr(b), self.p, _ptr(sigma2), _ptr(v),
+                     _ptr(status), _stream(stream)))
+
+    def _outputs(self, mb, dev):
+        return (torch.empty((mb, self.p), dtype=torch.float64, device=dev),
+                torch.empty(mb, dtype=torch.float64, device=dev),
+                torch.empty(mb, dtype=torch.float64, device=dev),
+                torch.empty(mb, dtype=torch.int32, device=dev))
+
+    def block_u8_into(self, G, b, sigma2, v, status, stream=None):
+        """One block of genotype bytes (mb, n) uint8 CUDA into caller-provided outputs."""
+        self._dosage_block_into(lib().gls_block_u8, self.n, G, b, sigma2, v, status, stream)
 
     def block_u8(self, G, stream=None):
-        mb = G.shape[0]
-        dev = G.device
-        b = torch.empty((mb, self.p), dtype=torch.float64, device=dev)
-        s2 = torch.empty(mb, dtype=torch.float64, device=dev)
-        v = torch.empty(mb, dtype=torch.float64, device=dev)
-        status = torch.empty(mb, dtype=torch.int32, device=dev)
-        self.block_u8_into(G, b, s2, v, status, stream)
-        return b, s2, v, status
+        out = self._outputs(G.shape[0], G.device)
+        self.block_u8_into(G, *out, stream)
+        return out
+
+    def block_u2_into(self, G2, b, sigma2, v, status, stream=None):
+        """One block of packed 2-bit dosages (mb, ceil(n / 4)) uint8 CUDA (the layout
+        of ``synth.pack_dosages_2bit``) into caller-provided outputs."""
+        self._dosage_block_into(lib().gls_block_u2, (self.n + 3) // 4, G2, b, sigma2, v, status, stream)
+
+    def block_u2(self, G2, stream=None):
+        out = self._outputs(G2.shape[0], G2.device)
+        self.block_u2_into(G2, *out, stream)
+        return out
 
     def block(self, XR, stream=None):
         """XR: (mb, n) float64 CUDA.  Returns b (mb, p), sigma2, v, status."""
@@ -234,10 +254,11 @@ class GLSContext:
         self.block_into(XR, b, s2, v, status, stream)
         return b, s2, v, status
 
-    def stream_file(self, path: str, m: int, dtype=torch.float64, offset: int = 0, col0: int = 0, out=None,
+    def stream_file(self, path: str, m: int, fmt=torch.float64, offset: int = 0, col0: int = 0, out=None,
                     host_ws=None, compute_stream=None, copy_stream=None):
-        """Stream SNPs [col0, m) from a file (SNP-major, float64 or uint8 genotype bytes)."""
-        elem = 8 if dtype == torch.float64 else 1
+        """Stream SNPs [col0, m) from a SNP-major file; fmt is torch.float64,
+        torch.uint8 (genotype bytes) or "u2" (packed 2-bit dosages)."""
+        elem = _FILE_BITS[fmt]
         need = int(lib().gls_stream_file_host_bytes(self.handle, elem))
         if host_ws is None or host_ws.numel() < need:
             host_ws = torch.empty(need, dtype=torch.uint8).pin_memory()
@@ -256,15 +277,22 @@ class GLSContext:
         _check(st)
         return (b, s2, v, status), stats
 
-    def stream(self, XR_host, col0: int = 0, out=None, compute_stream=None, copy_stream=None):
-        """Stream SNPs [col0, m) of a pinned host tensor XR_host (m, n), float64
-        or uint8 genotype bytes.
+    def stream(self, XR_host, col0: int = 0, out=None, compute_stream=None, copy_stream=None, packed=False):
+        """Stream SNPs [col0, m) of a pinned host tensor XR_host: (m, n) float64
+        or uint8 genotype bytes, or with packed=True (m, ceil(n / 4)) uint8
+        packed 2-bit dosages.
 
         Returns (b, sigma2, v, status) host tensors and the stats struct.
         """
         _need(XR_host, "XR_host", XR_host.dtype if XR_host.dtype in (torch.uint8, torch.float64) else torch.float64,
               cuda=False)
-        entry = lib().gls_stream_u8 if XR_host.dtype == torch.uint8 else lib().gls_stream
+        if packed:
+            _need(XR_host, "XR_host", torch.uint8, cuda=False)
+            entry, rowlen = lib().gls_stream_u2, (self.n + 3) // 4
+        else:
+            entry, rowlen = (lib().gls_stream_u8 if XR_host.dtype == torch.uint8 else lib().gls_stream), self.n
+        if XR_host.dim() != 2 or XR_host.shape[1] != rowlen:
+            raise ValueError(f"XR_host must have shape (m, {rowlen})")
         m = XR_host.shape[0]
         if out is None:
             out = (torch.full((m, self.p), float("nan"), dtype=torch.float64).pin_memory(),
@@ -280,7 +308,7 @@ class GLSContext:
         stats = GlsStreamStats()
         cs = compute_stream or torch.cuda.current_stream()
         xs = copy_stream or torch.cuda.Stream()
-        st = entry(self.handle, m, col0, _ptr(XR_host), self.n, _ptr(b), _ptr(s2), _ptr(v),
+        st = entry(self.handle, m, col0, _ptr(XR_host), rowlen, _ptr(b), _ptr(s2), _ptr(v),
                    _ptr(status), ctypes.c_void_p(cs.cuda_stream), ctypes.c_void_p(xs.cuda_stream),
                    ctypes.byref(stats))
         _check(st)

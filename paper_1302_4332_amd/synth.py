@@ -13,8 +13,8 @@ millions; the recipe below fills in what the paper leaves open):
 * covariates X_L = [1, sex ~ Bernoulli(0.5), age ~ N(50, 10)] (p = 4), or
   [1, N(0,1) x (p-2)] for the Gaussian kind;
 * SNP dosages x_R,j ~ Binomial(2, f_j), f_j ~ U(0.05, 0.5) per SNP, stored as
-  float64 (or uint8) with each SNP's n samples contiguous, i.e. column-major
-  n x m;
+  float64 (or uint8, or packed four to a byte) with each SNP's n samples
+  contiguous, i.e. column-major n x m;
 * phenotype y ~ N(0, 1), optionally plus effect * x_R,c for one causal SNP c.
 
 Randomness is counter-addressed: SNP chunk k of a study draws from
@@ -157,6 +157,24 @@ def genotypes(n: int, j0: int, j1: int, seed: int, out: np.ndarray | None = None
     return out
 
 
+def pack_dosages_2bit(g: np.ndarray) -> np.ndarray:
+    """Packs uint8 dosages 0..3 of shape (cols, n) four to a byte, shape
+    (cols, ceil(n / 4)): sample k in bits [2 (k % 4), 2 (k % 4) + 2) of byte
+    k // 4; pad bits are zero.  A storage format only (the library's 2-bit
+    entry points read it)."""
+    g = np.ascontiguousarray(g, dtype=np.uint8)
+    if g.ndim != 2:
+        raise ValueError("g must be (cols, n)")
+    if g.size and int(g.max()) > 3:
+        raise ValueError("2-bit packing holds dosages 0..3 only")
+    cols, n = g.shape
+    q = (n + 3) // 4
+    pad = np.zeros((cols, 4 * q), dtype=np.uint8)
+    pad[:, :n] = g
+    t = pad.reshape(cols, q, 4)
+    return (t[:, :, 0] | (t[:, :, 1] << 2) | (t[:, :, 2] << 4) | (t[:, :, 3] << 6)).astype(np.uint8)
+
+
 def phenotype(n: int, seed: int, x_causal: np.ndarray | None = None, effect: float = 0.3) -> np.ndarray:
     rng = np.random.default_rng([seed, STREAM_Y])
     y = rng.standard_normal(n)
@@ -184,6 +202,9 @@ class Study:
 
     def snps_u8(self, j0: int, j1: int) -> np.ndarray:
         return genotypes_u8(self.w.n, j0, j1, self.w.seed)
+
+    def snps_u2(self, j0: int, j1: int) -> np.ndarray:
+        return pack_dosages_2bit(genotypes_u8(self.w.n, j0, j1, self.w.seed))
 
 
 def make_study(w: Workload | str, *, n: int | None = None, m: int | None = None,

@@ -1,5 +1,6 @@
 """The seeded generators: determinism, counter addressing and the recipe's statistics."""
 import numpy as np
+import pytest
 
 from paper_1302_4332_amd import synth
 
@@ -36,3 +37,20 @@ def test_study_deterministic_and_causal():
     XL = s1.XL
     assert np.all(XL[:, 0] == 1) and set(np.unique(XL[:, 1])) <= {0.0, 1.0}
     assert 40 < XL[:, 2].mean() < 60
+
+
+def test_pack_dosages_2bit_layout():
+    # sample k in bits [2 (k % 4), 2 (k % 4) + 2) of byte k // 4, pad bits zero
+    g = np.array([[0, 1, 2, 3, 2], [3, 3, 3, 3, 0]], dtype=np.uint8)
+    assert synth.pack_dosages_2bit(g).tolist() == [[0b11100100, 0b00000010], [0xFF, 0x00]]
+    with pytest.raises(ValueError):
+        synth.pack_dosages_2bit(np.array([[4]], dtype=np.uint8))
+
+
+@pytest.mark.parametrize("n", [1, 4, 7, 330])
+def test_pack_dosages_2bit_round_trip(n):
+    g = np.random.default_rng(n).integers(0, 4, size=(9, n)).astype(np.uint8)
+    P = synth.pack_dosages_2bit(g)
+    assert P.shape == (9, (n + 3) // 4)
+    back = np.stack([(P[:, k // 4] >> (2 * (k % 4))) & 3 for k in range(n)], axis=1)
+    assert np.array_equal(back, g)
