@@ -60,6 +60,22 @@ static int64_t recursion_temp_leaves(int a, int b) {
   return std::max(here, std::max(recursion_temp_leaves(a, mid), recursion_temp_leaves(mid, b)));
 }
 
+// Setup products of at least this many output elements use the XCD-aware
+// mapping, and the inverse factor's T = L21 L11^-1 of such a node runs on
+// the side stream.
+static bool big_product(int64_t rows, int64_t cols) { return rows * cols >= (int64_t)1024 * 1024; }
+
+// Per recursion depth, the largest (b - mid) x (mid - a) leaf product of a
+// node whose T runs on the side stream.
+static void side_temp_leaves(int a, int b, int depth, int64_t* most) {
+  if (b - a <= 1 || depth >= 16) return;
+  const int mid = (a + b) / 2;
+  const int64_t here = (int64_t)(b - mid) * (mid - a);
+  if (big_product((int64_t)(b - mid) * NB_LEAF, (int64_t)(mid - a) * NB_LEAF)) most[depth] = std::max(most[depth], here);
+  side_temp_leaves(a, mid, depth + 1, most);
+  side_temp_leaves(mid, b, depth + 1, most);
+}
+
 bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   if (n < 2 || p < 1 || p > PMAX || n <= p || !o || o->block_cols < 1) return false;
   if (o->precision < GLS_FP64 || o->precision > GLS_INT8_EMU) return false;
@@ -85,8 +101,17 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   pl->off_Linv = take(sizeof(double) * N * N);
   pl->off_W = take(sizeof(double) * N * p);
   int64_t tmp = std::max<int64_t>(N * bc, recursion_temp_leaves(0, Kt) * NB_LEAF * NB_LEAF);
-  tmp = std::max<int64_t>(tmp, N * p);
+  tmp = std::max<int64_t>(tmp, N * p * (1 + (N + TA_KC - 1) / TA_KC));   // [X_L | y] and its split-k partials
   pl->off_Xt = take(sizeof(double) * tmp);
+  {
+    int64_t most[16] = {0}, at = 0;
+    side_temp_leaves(0, Kt, 0, most);
+    for (int d = 0; d < 16; ++d) {
+      pl->side_at[d] = at;
+      at += most[d] * NB_LEAF * NB_LEAF;
+    }
+    pl->off_side = take(sizeof(double) * std::max<int64_t>(at, 1));
+  }
   pl->off_buf0 = take(sizeof(double) * n * bc);
   pl->off_buf1 = take(sizeof(double) * n * bc);
   pl->off_ob = take(sizeof(double) * p * bc);
@@ -217,9 +242,38 @@ static int grid_for(int64_t total) {
 //                            L22 = chol(A22),   L22^-1
 //                            (L^-1)21 = -L22^-1 L21 L11^-1
 // Large setup products use the XCD-aware heavy-first mapping; small ones the plain grid.
-static bool big_product(int rows, int cols) { return (int64_t)rows * cols >= (int64_t)1024 * 1024; }
+//
+// T = L21 L11^-1 is needed only by the last product of its node, so for big
+// nodes it runs on a side stream (forked after L21 is formed, joined before
+// that last product) while the main stream factors L22; it then fills the
+// compute units that L22's latency-bound small steps leave idle.  Each depth
+// has its own T region and join event.
+struct SetupSide {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[16] = {};
+  double* base = nullptr;   // side scratch (plan offsets side_at[depth])
+  hipError_t err = hipSuccess;   // first failed record or wait
+  void check(hipError_t e) {
+    if (err == hipSuccess) err = e;
+  }
+  ~SetupSide() {
+    if (st) (void)hipStreamSynchronize(st);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (st) (void)hipStreamDestroy(st);
+  }
+  hipError_t init(double* scratch) {
+    base = scratch;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (int d = 0; d < 16 && e == hipSuccess; ++d) e = hipEventCreateWithFlags(&join[d], hipEventDisableTiming);
+    return e;
+  }
+};
 
-static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
+static void chol_inv_rec(Ctx* c, int a, int b, int depth, SetupSide* side, hipStream_t s) {
   const int64_t N = c->N;
   double* L = c->L;
   double* Li = c->Linv;
@@ -230,7 +284,7 @@ static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
     return;
   }
   const int mid = (a + b) / 2;
-  chol_inv_rec(c, a, mid, s);
+  chol_inv_rec(c, a, mid, depth + 1, side, s);
   const int64_t r1 = (int64_t)a * NB_LEAF, r2 = (int64_t)mid * NB_LEAF;
   const int w1 = (mid - a) * NB_LEAF, w2 = (b - mid) * NB_LEAF;
   double* A21 = L + r2 + r1 * N;
@@ -255,8 +309,21 @@ static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
     g.map_desc = 1;
     gemm(false, true, big_product(w2, w2), g, s);
   }
-  chol_inv_rec(c, mid, b, s);
-  {  // T = L21 L11^-1   (op(B) = Li11 lower: non-zero for k >= j)
+  const bool on_side = big_product(w2, w1) && depth < 16;
+  if (on_side) {   // T = L21 L11^-1 on the side stream, into this depth's region
+    T = side->base + c->plan.side_at[depth];
+    side->check(hipEventRecord(side->fork, s));
+    side->check(hipStreamWaitEvent(side->st, side->fork, 0));
+    GemmArgs g = gemm_args(A21, N, Li11, N, T, w2, w2, w1, w1, 1.0);
+    g.b_tri = TRI_LOWER;
+    g.b_diag = 0;
+    gemm(false, false, true, g, side->st);
+    side->check(hipEventRecord(side->join[depth], side->st));
+  }
+  chol_inv_rec(c, mid, b, depth + 1, side, s);
+  if (on_side) {
+    side->check(hipStreamWaitEvent(s, side->join[depth], 0));
+  } else {  // T = L21 L11^-1   (op(B) = Li11 lower: non-zero for k >= j)
     GemmArgs g = gemm_args(A21, N, Li11, N, T, w2, w2, w1, w1, 1.0);
     g.b_tri = TRI_LOWER;
     g.b_diag = 0;
@@ -268,6 +335,28 @@ static void chol_inv_rec(Ctx* c, int a, int b, hipStream_t s) {
     g.a_diag = 0;
     g.map_desc = 1;
     gemm(false, false, big_product(w2, w1), g, s);
+  }
+}
+
+template <int P>
+static void tri_apply_p(Ctx* c, const double* V, double* part, double* W, hipStream_t s) {
+  const int N = (int)c->N;
+  hipLaunchKernelGGL(tri_apply_partial_kernel<P>, dim3(N / 64, (N + TA_KC - 1) / TA_KC), dim3(256), 0, s, c->Linv, N,
+                     V, part);
+  hipLaunchKernelGGL(tri_apply_sum_kernel, dim3(grid_for((int64_t)N * P)), dim3(256), 0, s, part, N, P, W);
+}
+
+// W (N x p) = L^-1 V for the covariate block V (N x p, ld N); part holds
+// ceil(N / TA_KC) partial N x p blocks.
+static void tri_apply(Ctx* c, const double* V, double* part, double* W, hipStream_t s) {
+  switch (c->p) {
+#define GLS_P_CASE(P) \
+  case P: tri_apply_p<P>(c, V, part, W, s); break;
+    GLS_P_CASE(1) GLS_P_CASE(2) GLS_P_CASE(3) GLS_P_CASE(4) GLS_P_CASE(5) GLS_P_CASE(6) GLS_P_CASE(7)
+    GLS_P_CASE(8) GLS_P_CASE(9) GLS_P_CASE(10) GLS_P_CASE(11) GLS_P_CASE(12) GLS_P_CASE(13) GLS_P_CASE(14)
+    GLS_P_CASE(15) GLS_P_CASE(16) GLS_P_CASE(17) GLS_P_CASE(18) GLS_P_CASE(19) GLS_P_CASE(20)
+#undef GLS_P_CASE
+    default: break;
   }
 }
 
@@ -385,7 +474,17 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<double*>(c->info), (int64_t)4, 0.0);
   hipLaunchKernelGGL(form_m_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->L, (int)N, (int)n, Phi, ld_phi, h2);
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Linv, N * N, 0.0);
-  chol_inv_rec(c, 0, (int)(N / NB_LEAF), s);
+  {
+    SetupSide side;
+    if ((e = side.init(reinterpret_cast<double*>(ws + pl.off_side))) != hipSuccess)
+      return fail(hip_fail(e, "gls_setup: side stream"));
+    chol_inv_rec(c, 0, (int)(N / NB_LEAF), 0, &side, s);
+    // every side product is joined into s by its node's last product
+    if (side.err != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      return fail(hip_fail(side.err, "gls_setup: side stream fork/join"));
+    }
+  }
   c->ub[0] = reinterpret_cast<uint8_t*>(ws + pl.off_ub0);
   c->ub[1] = reinterpret_cast<uint8_t*>(ws + pl.off_ub1);
   if (opts->precision == GLS_INT8_EMU) {
@@ -427,12 +526,7 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   double* Wp = c->Xt;
   hipLaunchKernelGGL(pack_covariates_kernel, dim3(grid_for(N * p)), dim3(256), 0, s, Wp, (int)N, (int)n, (int)p, XL,
                      ld_xl, y);
-  {
-    GemmArgs g = gemm_args(c->Linv, N, Wp, N, c->W, N, (int)N, p, (int)N, 1.0);
-    g.a_tri = TRI_LOWER;
-    g.a_diag = 0;
-    gemm(false, false, false, g, s);
-  }
+  tri_apply(c, Wp, Wp + N * p, c->W, s);
   hipLaunchKernelGGL(gram_kernel, dim3(p * (p + 1) / 2), dim3(256), 0, s, c->W, (int)N, (int)p, c->gram);
   hipLaunchKernelGGL(small_factor_kernel, dim3(1), dim3(64), 0, s, c->gram, (int)p, c->small, c->info + 1);
   if ((e = hipGetLastError()) != hipSuccess) return fail(hip_fail(e, "gls_setup: launch"));

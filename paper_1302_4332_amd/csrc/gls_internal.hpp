@@ -30,6 +30,10 @@ struct Plan {
   // adjoint (GLS_KEEP_FOR_GRAD)
   size_t off_Phi = 0, off_Lbar = 0, off_T1 = 0, off_T2 = 0, off_Xtb = 0, off_Xb = 0;
   size_t off_Cb = 0, off_eb = 0, off_ct = 0, off_Wb = 0, off_W0b = 0, off_acc = 0;
+  // setup: scratch of the inverse-factor products that run on the side stream,
+  // one region per recursion depth (offsets in doubles from off_side)
+  size_t off_side = 0;
+  int64_t side_at[16] = {0};
   size_t total = 0;
 };
 

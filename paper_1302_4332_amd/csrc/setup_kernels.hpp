@@ -61,6 +61,65 @@ __global__ void pack_covariates_kernel(double* __restrict__ Wp, int N, int n, in
   }
 }
 
+// W = L^-1 V for the thin covariate block V = [X_L | y] (N x P, ld N) and the
+// lower-triangular inverse factor (N x N, ld N): a matrix-vector-shaped
+// product bound by reading L^-1's lower triangle once, so it runs split over
+// k on the vector units.  Workgroup (r, s) takes rows 64 r .. 64 r + 63 and
+// k in [TA_KC s, TA_KC s + TA_KC), clipped to k <= row; each wave walks every
+// fourth k, so a wave's loads are one 512-byte column segment.  Partial sums
+// go to part[s] (N x P, ld N); chunks entirely above a row tile are skipped,
+// and tri_apply_sum_kernel adds, in chunk order, exactly the chunks that
+// reach each row tile.
+constexpr int TA_KC = 256;
+
+template <int P>
+__global__ __launch_bounds__(256) void tri_apply_partial_kernel(const double* __restrict__ Li, int N,
+                                                                const double* __restrict__ V,
+                                                                double* __restrict__ part) {
+  __shared__ double v[TA_KC * P];       // v[kk * P + j] = V[k0 + kk][j]; then the group sums
+  const int i0 = blockIdx.x * 64, s = blockIdx.y, k0 = s * TA_KC;
+  if (k0 > i0 + 63) return;
+  const int t = threadIdx.x, r = t & 63, g = t >> 6;
+  for (int idx = t; idx < TA_KC * P; idx += 256) {
+    const int kk = idx % TA_KC, j = idx / TA_KC;
+    v[kk * P + j] = (k0 + kk < N) ? V[(int64_t)(k0 + kk) + (int64_t)j * N] : 0.0;
+  }
+  __syncthreads();
+  const int i = i0 + r;
+  const int kend = min(min(k0 + TA_KC, i0 + 64), N);
+  double acc[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) acc[j] = 0.0;
+  for (int k = k0 + g; k < kend; k += 4) {
+    const double a = (k <= i) ? Li[(int64_t)i + (int64_t)k * N] : 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = fma(a, v[(k - k0) * P + j], acc[j]);
+  }
+  __syncthreads();   // v is reused for the four groups' sums
+#pragma unroll
+  for (int j = 0; j < P; ++j) v[(g * 64 + r) * P + j] = acc[j];
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const double x = ((acc[j] + v[(64 + r) * P + j]) + v[(128 + r) * P + j]) + v[(192 + r) * P + j];
+      part[(int64_t)s * N * P + (int64_t)j * N + i] = x;
+    }
+  }
+}
+
+__global__ void tri_apply_sum_kernel(const double* __restrict__ part, int N, int P, double* __restrict__ W) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)N * P;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % N);
+    const int last = (i / 64 * 64 + 63) / TA_KC;   // chunks s <= last reach row tile i / 64
+    double x = 0.0;
+    for (int s = 0; s <= last; ++s) x += part[(int64_t)s * total + idx];
+    W[idx] = x;
+  }
+}
+
 // 1/p to full double precision: hardware reciprocal estimate plus two
 // Newton steps (off the IEEE division's long sequence; used where the last
 // bit is immaterial, the pivots of the right-looking update).
