@@ -52,6 +52,10 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int64_t padded_n(int64_t n) { return (n + NPAD - 1) / NPAD * NPAD; }
 
+// Launch shapes below take N / tile rows without a remainder.
+static_assert(NPAD % NB_LEAF == 0 && NPAD % LP_BM == 0 && NPAD % OZ_BM == 0 && NPAD % DB_BM == 0 && NPAD % 64 == 0,
+              "the row padding must be a multiple of every row tile");
+
 // Largest T1 buffer of the recursive factorization: (b - mid) * (mid - a) leaves.
 static int64_t recursion_temp_leaves(int a, int b) {
   if (b - a <= 1) return 0;
@@ -812,32 +816,25 @@ namespace gls {
 // per group (measured best of 1x16 .. 16x1 at n = 10,000, 8,192 SNPs).
 constexpr int OZ_MAP_GM = 4, OZ_MAP_GN = 4;
 
-// The block's dosages are in c->ubp (N x mb bytes, rows >= n zero): the
-// product on the integer matrix cores, then the per-SNP work.
-static void block_forward_i8(Ctx* c, int mb, double* b, int64_t ld_b, double* s2, double* v, int* st, hipStream_t s) {
+// The product of L^-1 with the block's dosages in c->ubp (N x mb bytes, rows
+// >= n zero) on the integer matrix cores, into c->Xt.
+static void ozaki_product(Ctx* c, int mb, hipStream_t s) {
   const int64_t N = c->N;
-  {
-    {
-      PhaseTimer t(c, PH_WHITEN, s);
-      OzArgs a;
-      a.A = c->sl;
-      a.ex = c->ex;
-      a.B = c->ubp;
-      a.C = c->Xt;
-      a.ldc = N;
-      a.N = (int)N;
-      a.ncols = mb;
-      a.map_gm = OZ_MAP_GM;
-      a.map_gn = OZ_MAP_GN;
-      GemmArgs m{};
-      m.map_gm = a.map_gm;
-      m.map_gn = a.map_gn;
-      hipLaunchKernelGGL(ozaki_i8_kernel, dim3(XcdMap::grid(m, (int)(N / OZ_BM), (mb + OZ_BN - 1) / OZ_BN)),
-                         dim3(OZ_THREADS), 0, s, a);
-    }
-    PhaseTimer t(c, PH_SNP, s);
-    snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
-  }
+  OzArgs a;
+  a.A = c->sl;
+  a.ex = c->ex;
+  a.B = c->ubp;
+  a.C = c->Xt;
+  a.ldc = N;
+  a.N = (int)N;
+  a.ncols = mb;
+  a.map_gm = OZ_MAP_GM;
+  a.map_gn = OZ_MAP_GN;
+  GemmArgs m{};
+  m.map_gm = a.map_gm;
+  m.map_gn = a.map_gn;
+  hipLaunchKernelGGL(ozaki_i8_kernel, dim3(XcdMap::grid(m, (int)(N / OZ_BM), (mb + OZ_BN - 1) / OZ_BN)),
+                     dim3(OZ_THREADS), 0, s, a);
 }
 
 gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, double* b, int64_t ld_b, double* s2,
@@ -847,8 +844,10 @@ gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, doubl
     {
       PhaseTimer t(c, PH_WHITEN, s);
       hipLaunchKernelGGL(pack_u8_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->ubp);
+      ozaki_product(c, mb, s);
     }
-    block_forward_i8(c, mb, b, ld_b, s2, v, st, s);
+    PhaseTimer t(c, PH_SNP, s);
+    snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
     return GLS_OK;
   }
   hipLaunchKernelGGL(u8_to_f64_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->x64);
@@ -863,8 +862,10 @@ gls_status block_forward_u2(Ctx* c, int mb, const uint8_t* G2, int64_t ldg, doub
       PhaseTimer t(c, PH_WHITEN, s);
       hipLaunchKernelGGL(unpack_u2_kernel, dim3(grid_for(N / 4 * mb)), dim3(256), 0, s, G2, ldg, (int)c->n, (int)N,
                          mb, reinterpret_cast<uint32_t*>(c->ubp));
+      ozaki_product(c, mb, s);
     }
-    block_forward_i8(c, mb, b, ld_b, s2, v, st, s);
+    PhaseTimer t(c, PH_SNP, s);
+    snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
     return GLS_OK;
   }
   hipLaunchKernelGGL(unpack_u2_f64_kernel, dim3(grid_for(N / 4 * mb)), dim3(256), 0, s, G2, ldg, (int)c->n, (int)N,

@@ -151,8 +151,17 @@ class GLSContext:
         _need(Phi, "Phi")
         _need(y, "y")
         n = Phi.shape[0]
+        if Phi.dim() != 2 or Phi.shape[1] != n:
+            raise ValueError(f"Phi must be square, got {tuple(Phi.shape)}")
+        if tuple(y.shape) != (n,):
+            raise ValueError(f"y must have shape ({n},), got {tuple(y.shape)}")
         if XL is None:
             XL = torch.empty((n, 0), dtype=torch.float64, device=Phi.device)
+        _need(XL.contiguous(), "XL")
+        if XL.dim() != 2 or XL.shape[0] != n:
+            raise ValueError(f"XL must have shape ({n}, p - 1), got {tuple(XL.shape)}")
+        if XL.device != Phi.device or y.device != Phi.device:
+            raise ValueError("Phi, XL and y must be on the same device")
         p = XL.shape[1] + 1
         XLc = XL.t().contiguous() if XL.shape[1] else None
         self.n, self.p = n, p
