@@ -64,3 +64,34 @@ def test_output_vjp_consistent_with_loss_gradient():
     assert np.allclose(dy, dy2, rtol=1e-9, atol=1e-12)
     assert np.allclose(dXR, dXR2, rtol=1e-9, atol=1e-12)
     assert dh2 == pytest.approx(dh22, rel=1e-9)
+
+
+def test_h2_gradient_closed_form():
+    """d loss / d h2 of the reference gradient against a closed form with no
+    autograd and no differences: dM/dh2 = Phi - I, so d(M^-1) = -M^-1 (Phi - I)
+    M^-1, and per SNP, with A = X^T M^-1 X and r = X^T M^-1 y,
+        dA = -X^T M^-1 (Phi - I) M^-1 X,   dr = -X^T M^-1 (Phi - I) M^-1 y,
+        db = A^-1 (dr - dA b),   dc = -y^T M^-1 (Phi - I) M^-1 y,
+        dsigma2 = (dc - db.r - b.dr) / (n - p),   dv = -(A^-1 dA A^-1)_pp,
+    chained into t^2 = b_p^2 / (sigma2 v)."""
+    Phi, h2, XL, y, XR = _problem(seed=21)
+    n, m = XR.shape[1], XR.shape[0]
+    p = XL.shape[1] + 1
+    M = h2 * Phi + (1 - h2) * np.eye(n)
+    Mi = np.linalg.inv(M)
+    D = Mi @ (Phi - np.eye(n)) @ Mi                   # -d(M^-1)/dh2
+    c, dc = y @ Mi @ y, -(y @ D @ y)
+    total = 0.0
+    for i in range(m):
+        X = np.column_stack([XL, XR[i]])
+        A, r = X.T @ Mi @ X, X.T @ Mi @ y
+        Ai = np.linalg.inv(A)
+        b = Ai @ r
+        dA, dr = -(X.T @ D @ X), -(X.T @ D @ y)
+        db = Ai @ (dr - dA @ b)
+        s2 = (c - b @ r) / (n - p)
+        ds2 = (dc - db @ r - b @ dr) / (n - p)
+        v, dv = Ai[-1, -1], -(Ai @ dA @ Ai)[-1, -1]
+        total += 2 * b[-1] * db[-1] / (s2 * v) - b[-1] ** 2 * (ds2 * v + s2 * dv) / (s2 * v) ** 2
+    _, _, _, dh2 = G.loss_and_grads(Phi, h2, XL, y, XR.T)
+    assert dh2 == pytest.approx(total, rel=1e-9)
