@@ -26,7 +26,7 @@ namespace gls {
 // c ^ (j & 7).  Two stages (48 KB) were measured best at n = 10,000 (three:
 // 3% slower, four: 15% slower; XCD groups other than 1 x 16 slower still); a
 // 64 x 64 tile with four waves (two k-columns of A per load instruction) runs
-// within 0.3% of this one; four waves of 64 x 32 on the same tile run 7% slower.
+// within 0.3% of this one.
 constexpr int DB_BM = 128, DB_BN = 64, DB_BK = 16, DB_THREADS = 512, DB_STAGES = 2;
 
 __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
