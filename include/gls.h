@@ -197,7 +197,8 @@ gls_status gls_stream_u2(gls_handle h, int64_t m, int64_t col0,
  * c = ceil(n / 4)).  A reader thread reads block b+2 into one of three
  * page-locked host buffers while block b+1 waits in another and block b is
  * copied to the device (two device buffers alternate as in gls_stream); a
- * host buffer is reused only once its copy has completed.  host_ws is the
+ * host buffer is reused only once its copy has completed.  Blocks follow
+ * gls_stream's schedule, opening ramp included.  host_ws is the
  * caller's page-locked host memory of gls_stream_file_host_bytes() bytes.
  * Outputs, col0 and return as gls_stream; read errors give GLS_ERR_ARG
  * (unopenable file) or GLS_ERR_STATE (short read), with gls_last_error().

@@ -79,6 +79,25 @@ gls_status solve_block(Ctx* c, int mb, const Packed2* X, int64_t ld, double* b, 
   return block_forward_u2(c, mb, reinterpret_cast<const uint8_t*>(X), ld, b, ldb, s2, v, st, s);
 }
 
+// Block schedule of a stream of `total` columns: starts of the blocks plus
+// `total` at the end.  Full blocks of bc, except that a stream of large blocks
+// (bc >= 2,048) starts with short ones, bc / 8 growing by a quarter per block
+// (multiples of 64): the first copy (and read), which nothing overlaps, is an
+// eighth as long, and each later one still fits under the solve before it
+// (a solve takes longer per SNP than its copy).  Results do not depend on the
+// blocking.
+std::vector<int64_t> block_schedule(int64_t bc, int64_t total) {
+  std::vector<int64_t> bstart;
+  int64_t pos = 0, len = (bc >= 2048) ? std::max<int64_t>(64, bc / 8 / 64 * 64) : bc;
+  while (pos < total) {
+    bstart.push_back(pos);
+    pos += std::min(len, total - pos);
+    len = std::min(bc, (len * 5 / 4 + 63) / 64 * 64);
+  }
+  bstart.push_back(total);
+  return bstart;
+}
+
 }  // namespace
 
 template <typename T>
@@ -96,22 +115,7 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
   hipStream_t sx = (c->opts.flags & GLS_STREAM_SERIAL) ? sc : static_cast<hipStream_t>(copy_stream);
   const int64_t bc = c->bc;
   const int p = c->p;
-  // Block schedule.  Full blocks of bc, except that a stream of large blocks
-  // (bc >= 2,048) starts with short ones, bc / 8 growing by a quarter per
-  // block (multiples of 64): the first copy, which nothing overlaps, is an
-  // eighth as long, and each later copy still fits under the solve before it
-  // (a solve takes longer per SNP than its copy).  Results do not depend on
-  // the blocking.
-  std::vector<int64_t> bstart;
-  {
-    int64_t pos = 0, len = (bc >= 2048) ? std::max<int64_t>(64, bc / 8 / 64 * 64) : bc;
-    while (pos < m - col0) {
-      bstart.push_back(pos);
-      pos += std::min(len, m - col0 - pos);
-      len = std::min(bc, (len * 5 / 4 + 63) / 64 * 64);
-    }
-    bstart.push_back(m - col0);
-  }
+  const std::vector<int64_t> bstart = block_schedule(bc, m - col0);
   const int64_t nblk = (int64_t)bstart.size() - 1;
   gls_stream_stats st{};
   if (nblk == 0) {
@@ -266,7 +270,8 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
   const int p = c->p;
   const bool serial = (c->opts.flags & GLS_STREAM_SERIAL) != 0;
   hipStream_t sx = serial ? sc : sx_in;
-  const int64_t nblk = (m - col0 + bc - 1) / bc;
+  const std::vector<int64_t> bstart = block_schedule(bc, m - col0);   // opening ramp as in gls_stream
+  const int64_t nblk = (int64_t)bstart.size() - 1;
   gls_stream_stats st{};
   if (nblk == 0) {
     if (stats_out) *stats_out = st;
@@ -275,8 +280,8 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
   const size_t slot_bytes = host_ring_bytes(c, rows * (int64_t)sizeof(T)) / 3;
   T* hb[3];
   for (int i = 0; i < 3; ++i) hb[i] = reinterpret_cast<T*>(host + i * slot_bytes);
-  auto cols_of = [&](int64_t blk) { return std::min<int64_t>(bc, m - col0 - blk * bc); };
-  auto file_off = [&](int64_t blk) { return (off_t)(offset + (col0 + blk * bc) * rows * (int64_t)sizeof(T)); };
+  auto cols_of = [&](int64_t blk) { return bstart[blk + 1] - bstart[blk]; };
+  auto file_off = [&](int64_t blk) { return (off_t)(offset + (col0 + bstart[blk]) * rows * (int64_t)sizeof(T)); };
 
   EventPool pool;
   hipError_t e;
@@ -336,7 +341,7 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
   for (int64_t blk = 0; blk < nblk; ++blk) {
     const int slot = (int)(blk % 3), cur = (int)(blk & 1);
     const int64_t cols = cols_of(blk);
-    const int64_t col = col0 + blk * bc;
+    const int64_t col = col0 + bstart[blk];
     if (serial) {
       int err = 0;
       auto t0 = std::chrono::steady_clock::now();

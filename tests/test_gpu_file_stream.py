@@ -66,3 +66,24 @@ def test_file_stream_resume_and_errors(study):
     with pytest.raises(GLSError) as e:
         ctx.stream_file(os.path.join(os.path.dirname(u8), "missing"), m, torch.uint8)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("serial", [False, True])
+def test_file_stream_ramp_equals_memory_stream(tmp_path, serial):
+    """Large blocks: the file stream opens with the same short blocks as the
+    in-memory stream and gives bitwise its results."""
+    n, m = 130, 5000
+    Phi = synth.kinship(n, 41)
+    XL = synth.covariates(n, 4, 41, "sex_age")
+    y = synth.phenotype(n, 41)
+    G = synth.genotypes_u8(n, 0, m, 41)
+    path = str(tmp_path / "x.u8")
+    G.tofile(path)
+    ctx = GLSContext(_t(Phi), 0.4, _t(XL), _t(y), block_cols=2048, serial_stream=serial)
+    (ref_b, _, _, ref_st), ref_stats = ctx.stream(torch.tensor(G).pin_memory())
+    (b, _, _, st), stats = ctx.stream_file(path, m, torch.uint8)
+    assert stats.blocks == ref_stats.blocks > (m + 2047) // 2048    # the ramp adds blocks
+    assert stats.file_bytes == n * m
+    assert np.array_equal(b.numpy(), ref_b.numpy()) and np.array_equal(st.numpy(), ref_st.numpy())
+    (b2, *_), stats2 = ctx.stream_file(path, m, torch.uint8, col0=1234)
+    assert np.array_equal(b2.numpy()[1234:], ref_b.numpy()[1234:])
