@@ -4,10 +4,11 @@ sampled SNPs that the CPU oracle solves one by one.
 
 - n = 10,000, p = 4 (sex/age covariates, causal SNP), blocks of 8,192: the
   first block and the last (1,696 SNPs: 100,000 mod 8,192), FP64 path and the
-  int8-slice path on the same SNPs as bytes;
+  int8-slice path on the same SNPs as bytes and as packed 2-bit dosages;
 - n = 10,000, p = 4, m = 1,000,000 (no causal SNP), blocks of 8,192: the first
-  block and the last (576 SNPs), in the refined mixed forms (FP32 one sweep,
-  FP16 three, BF16 four);
+  block and the last (576 SNPs), in the refined mixed forms (FP32 one sweep;
+  FP16 two and three; BF16 three and four: the fewest sweeps that meet the bar
+  and the counts that reach the FP64 level);
 - n = 20,000, p = 8 (Gaussian covariates), blocks of 16,384: the first block and
   a ragged block of 1,152 (2,000,000 mod 16,384).
 
@@ -26,7 +27,6 @@ from paper_1302_4332_amd.gls import GLSContext
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 TOL = {"fp64": 1e-10, "int8_emu": 1e-10, "fp32_ir": 1e-8, "fp16_ir": 1e-8, "bf16_ir": 1e-8}
-SWEEPS = {"fp64": 0, "int8_emu": 0, "fp32_ir": 1, "fp16_ir": 3, "bf16_ir": 4}
 
 
 def _t(a):
@@ -58,21 +58,22 @@ def _sample(j0, j1, k, seed):
     return np.unique(np.r_[j0, j1 - 1, rng.integers(j0, j1, size=k)])
 
 
-def _run(name, tail, precisions, k=48):
+def _run(name, tail, forms, k=48):
+    """forms: (precision, refinement sweeps, input) with input "f64", "u8" or "u2"."""
     w, st, bc, blocks = _study_blocks(name, tail)
     print(f"{name}: n={w.n} p={w.p} blocks {blocks}", flush=True)
     ost = O.Study(st.Phi, w.h2, st.XL, st.y)
     Phi, XL, y = _t(st.Phi), _t(st.XL), _t(st.y)
     errs = {}
-    for prec in precisions:
-        ctx = GLSContext(Phi, w.h2, XL, y, block_cols=bc, precision=prec, refine_sweeps=SWEEPS[prec])
+    for prec, sweeps, inp in forms:
+        ctx = GLSContext(Phi, w.h2, XL, y, block_cols=bc, precision=prec, refine_sweeps=sweeps)
         for bi, (j0, j1) in enumerate(blocks):
-            if prec == "int8_emu":
-                G = _t(st.snps_u8(j0, j1))
-                b, s2, v, status = ctx.block_u8(G)
+            if inp == "u8":
+                b, s2, v, status = ctx.block_u8(_t(st.snps_u8(j0, j1)))
+            elif inp == "u2":
+                b, s2, v, status = ctx.block_u2(_t(st.snps_u2(j0, j1)))
             else:
-                X = _t(st.snps(j0, j1))
-                b, s2, v, status = ctx.block(X)
+                b, s2, v, status = ctx.block(_t(st.snps(j0, j1)))
             torch.cuda.synchronize()
             idx = _sample(j0, j1, k, 100 + bi)
             if st.causal is not None and j0 <= st.causal < j1:
@@ -81,18 +82,19 @@ def _run(name, tail, precisions, k=48):
                  "v": v.cpu().numpy()[idx - j0], "status": status.cpu().numpy()[idx - j0]}
             cols = np.concatenate([st.snps(int(j), int(j) + 1) for j in idx])
             r = ost.block(cols.T)
-            errs[(prec, bi)] = _check(g, r, TOL[prec])
+            errs[(f"{prec}x{sweeps}/{inp}", bi)] = _check(g, r, TOL[prec])
         ctx.close()
     print({f"{p}/{b}": f"{e:.1e}" for (p, b), e in errs.items()}, flush=True)
 
 
 def test_fullsize_n10k_fp64_and_int8_slices():
-    _run("c1_n10k_m100k", 100000 % 8192, ("fp64", "int8_emu"))
+    _run("c1_n10k_m100k", 100000 % 8192, (("fp64", 0, "f64"), ("int8_emu", 0, "u8"), ("int8_emu", 0, "u2")))
 
 
 def test_fullsize_n10k_m1M_mixed():
-    _run("c2_n10k_m1M", 1000000 % 8192, ("fp32_ir", "fp16_ir", "bf16_ir"))
+    _run("c2_n10k_m1M", 1000000 % 8192, (("fp32_ir", 1, "f64"), ("fp16_ir", 2, "f64"), ("fp16_ir", 3, "f64"),
+                                         ("bf16_ir", 3, "f64"), ("bf16_ir", 4, "f64")))
 
 
 def test_fullsize_n20k_p8_fp64():
-    _run("c4_n20k_p8", 2000000 % 16384, ("fp64",))
+    _run("c4_n20k_p8", 2000000 % 16384, (("fp64", 0, "f64"),))
