@@ -947,12 +947,13 @@ gls_status block_backward(Ctx* c, int mb, const double* XR, int64_t ld_xr, const
   if (XR_grad)
     hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(c->n * mb)), dim3(256), 0, s, XR_grad, ld_xr, c->Xb, N, (int)c->n,
                        mb);
-  {  // Lbar -= X_R bar X~_R^T   (lower tiles; op(B)[k][j] = X~[j + k N])
+  {  // Lbar -= X_R bar X~_R^T   (lower tiles; op(B)[k][j] = X~[j + k N]); high row tiles hold the most tiles
     GemmArgs g = gemm_args(c->Xb, N, c->Xt, N, c->Lbar, N, (int)N, (int)N, mb, -1.0);
     g.beta = 1.0;
     g.c_lower = 1;
     g.c_diag = 0;
-    gemm(false, true, false, g, s);
+    g.map_desc = 1;
+    gemm(false, true, true, g, s);
   }
   return GLS_OK;
 }
@@ -990,7 +991,7 @@ gls_status finish_backward(Ctx* c, double* y_grad, double* h2_grad, hipStream_t 
     g.b_diag = 0;
     g.c_lower = 1;
     g.c_diag = 0;
-    gemm(true, false, false, g, s);
+    gemm(true, false, true, g, s);   // k from the row: low row tiles first
   }
   hipLaunchKernelGGL(lower_part_kernel, dim3(gN), dim3(256), 0, s, c->T1, (int)N, 1);
   {  // T2 = T1 L^-1   (lower x lower = lower)
@@ -1001,7 +1002,8 @@ gls_status finish_backward(Ctx* c, double* y_grad, double* h2_grad, hipStream_t 
     g.b_diag = 0;
     g.c_lower = 1;
     g.c_diag = 0;
-    gemm(false, false, false, g, s);
+    g.map_desc = 1;
+    gemm(false, false, true, g, s);   // k in [column, row]: high row tiles first
   }
   {  // T1 = L^-T T2   (the adjoint of M, up to symmetrisation)
     GemmArgs g = gemm_args(c->Linv, N, c->T2, N, c->T1, N, (int)N, (int)N, (int)N, 1.0);
@@ -1009,7 +1011,7 @@ gls_status finish_backward(Ctx* c, double* y_grad, double* h2_grad, hipStream_t 
     g.a_diag = 0;
     g.b_tri = TRI_LOWER;
     g.b_diag = 0;
-    gemm(true, false, false, g, s);
+    gemm(true, false, true, g, s);   // k from the row: low row tiles first
   }
   double* part = c->acc + adj_nc(p);
   hipLaunchKernelGGL(h2_contract_kernel, dim3(1024), dim3(256), 0, s, c->T1, c->Phi, (int)N, (int)c->n, part);
