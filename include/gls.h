@@ -118,10 +118,10 @@ gls_status gls_block(gls_handle h, int32_t mb, const double* XR, int64_t ld_xr,
                      double* b, int64_t ld_b, double* sigma2, double* v,
                      int32_t* snp_status, void* stream);
 
-/* One SNP block given as genotype bytes: G is n x mb uint8 (ld_g >= n),
- * entries 0..127 (dosages 0, 1, 2).  GLS_INT8_EMU sums exact int32 products,
- * so it needs n * 127 * max(G) < 2^31: any byte value for n <= 133,000,
- * dosages 0..2 for n up to 8.4 million.  Same outputs and asynchrony as
+/* One SNP block (Sec. 2.2, as gls_block) given as genotype bytes: G is
+ * n x mb uint8 (ld_g >= n), entries 0..127 (dosages 0, 1, 2).  GLS_INT8_EMU
+ * sums exact int32 products, so it needs n * 127 * max(G) < 2^31: any byte
+ * value for n <= 133,000, dosages 0..2 for n up to 8.4 million.  Same outputs and asynchrony as
  * gls_block.  With GLS_FP64 or the mixed forms the bytes are widened to FP64
  * on the device and the results are bitwise those of gls_block on the same
  * values; with GLS_INT8_EMU the product runs on the integer matrix cores
@@ -130,10 +130,11 @@ gls_status gls_block_u8(gls_handle h, int32_t mb, const uint8_t* G, int64_t ld_g
                         double* b, int64_t ld_b, double* sigma2, double* v,
                         int32_t* snp_status, void* stream);
 
-/* One SNP block given as packed 2-bit dosages: column j occupies bytes
- * [j * ld_g2, j * ld_g2 + ceil(n / 4)) of G2 (ld_g2 >= ceil(n / 4)); sample k's
- * dosage is the 2-bit code in bits [2 (k % 4), 2 (k % 4) + 2) of the column's
- * byte k / 4, read as the integer 0..3 (no missing-value code).  Bits of a
+/* One SNP block (Sec. 2.2, as gls_block) given as packed 2-bit dosages:
+ * column j occupies bytes [j * ld_g2, j * ld_g2 + ceil(n / 4)) of G2
+ * (ld_g2 >= ceil(n / 4)); sample k's dosage is the 2-bit code in bits
+ * [2 (k % 4), 2 (k % 4) + 2) of the column's byte k / 4, read as the integer
+ * 0..3 (no missing-value code).  Bits of a
  * column's last byte past sample n - 1 are ignored.  The codes are expanded
  * on the device, and the results are bitwise those of gls_block_u8 on the same
  * dosages as bytes (every precision).  Moves a quarter byte per sample.  Same
@@ -172,7 +173,7 @@ gls_status gls_stream(gls_handle h, int64_t m, int64_t col0,
                       int32_t* status_host, void* compute_stream, void* copy_stream,
                       gls_stream_stats* stats_out);
 
-/* gls_stream for genotype bytes: G_host is n x m uint8 (ld_g >= n) in
+/* gls_stream (Sec. 3.1) for genotype bytes: G_host is n x m uint8 (ld_g >= n) in
  * page-locked host memory; blocks are processed as by gls_block_u8. */
 gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0,
                          const uint8_t* G_host, int64_t ld_g,
@@ -180,7 +181,7 @@ gls_status gls_stream_u8(gls_handle h, int64_t m, int64_t col0,
                          int32_t* status_host, void* compute_stream, void* copy_stream,
                          gls_stream_stats* stats_out);
 
-/* gls_stream for packed 2-bit dosages: G2_host holds m columns of
+/* gls_stream (Sec. 3.1) for packed 2-bit dosages: G2_host holds m columns of
  * ceil(n / 4) bytes at stride ld_g2 (>= ceil(n / 4)) bytes, in page-locked host
  * memory, in the layout of gls_block_u2; blocks are processed as by
  * gls_block_u2. */
