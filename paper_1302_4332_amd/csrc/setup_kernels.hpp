@@ -80,9 +80,13 @@ __global__ __launch_bounds__(256) void tri_apply_partial_kernel(const double* __
   const int i0 = blockIdx.x * 64, s = blockIdx.y, k0 = s * TA_KC;
   if (k0 > i0 + 63) return;
   const int t = threadIdx.x, r = t & 63, g = t >> 6;
-  for (int idx = t; idx < TA_KC * P; idx += 256) {
-    const int kk = idx % TA_KC, j = idx / TA_KC;
-    v[kk * P + j] = (k0 + kk < N) ? V[(int64_t)(k0 + kk) + (int64_t)j * N] : 0.0;
+  static_assert(TA_KC == 256, "one staged k per thread and column");
+  {
+    double x[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) x[j] = (k0 + t < N) ? V[(int64_t)(k0 + t) + (int64_t)j * N] : 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[t * P + j] = x[j];
   }
   __syncthreads();
   const int i = i0 + r;
@@ -90,10 +94,22 @@ __global__ __launch_bounds__(256) void tri_apply_partial_kernel(const double* __
   double acc[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) acc[j] = 0.0;
-  for (int k = k0 + g; k < kend; k += 4) {
-    const double a = (k <= i) ? Li[(int64_t)i + (int64_t)k * N] : 0.0;
+  // eight loads in flight per thread, then their products
+  for (int kb = k0 + g; kb < kend; kb += 32) {
+    double a[8];
 #pragma unroll
-    for (int j = 0; j < P; ++j) acc[j] = fma(a, v[(k - k0) * P + j], acc[j]);
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + 4 * u;
+      a[u] = (k < kend && k <= i) ? Li[(int64_t)i + (int64_t)k * N] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int kk = kb + 4 * u - k0;
+      if (kb + 4 * u < kend) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[j] = fma(a[u], v[kk * P + j], acc[j]);
+      }
+    }
   }
   __syncthreads();   // v is reused for the four groups' sums
 #pragma unroll
@@ -241,9 +257,15 @@ __global__ __launch_bounds__(512) void leaf_potrf_trtri_kernel(double* __restric
   __shared__ double rd[NB_LEAF];   // 1 / L[k][k]
   __shared__ double colw[LT];      // wave 0's column exchange
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int idx = t; idx < NB_LEAF * NB_LEAF; idx += 512) {
-    const int r = idx % NB_LEAF, c = idx / NB_LEAF;
-    S[r + c * LD] = A[(int64_t)r + (int64_t)c * ld];
+  {  // all loads first, then the LDS stores: one memory latency instead of one per element
+    constexpr int PER = NB_LEAF * NB_LEAF / 512;
+    static_assert(512 % NB_LEAF == 0, "a thread keeps its row");
+    const int r = t % NB_LEAF, c0 = t / NB_LEAF;
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = A[(int64_t)r + (int64_t)(c0 + q * (512 / NB_LEAF)) * ld];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) S[r + (c0 + q * (512 / NB_LEAF)) * LD] = v[q];
   }
   __syncthreads();
   int bad = 0;   // meaningful in wave 0
