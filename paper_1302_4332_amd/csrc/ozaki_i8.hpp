@@ -141,11 +141,18 @@ struct OzArgs {
 //
 // The kernel computes the transpose, D = X^T a_s^T, so that the accumulator's
 // fast index (l % 16) runs down a column of the column-major result and the
-// FP64 stores are 128-byte runs.  A workgroup of eight waves owns a 32 x 256
-// output tile; wave w takes the 16-row strip w & 1 and the 64-column strip
-// w >> 1, holding S x 4 accumulators (one per factor slice and 16-column
-// group).  Per 64-deep k step a wave reads four byte fragments and one
-// fragment per slice from LDS and issues 4 S MFMAs.
+// FP64 stores are 128-byte runs.  A workgroup of sixteen waves owns a 32 x 256
+// output tile: wave w takes the 16-row strip w & 1, the 64-column strip
+// (w >> 1) & 3 and the slice half w >> 3 (slices 0..3 or 4..7), holding 4 x 4
+// accumulators (one per slice and 16-column group).  Splitting the slices over
+// two waves halves the accumulators, so four waves share each SIMD instead of
+// two and one wave's wait at the stage barrier no longer idles the matrix
+// pipe as often (5% faster than eight waves holding all eight slices, with
+// bitwise the same results).  Per 64-deep k step a wave reads four byte
+// fragments and one fragment per slice from LDS and issues 16 MFMAs.  At the
+// end the second half adds its slices 7..4 into an LDS buffer (reusing the
+// ring) and the first half continues with 3..0: the same order as one wave
+// summing all eight.
 //
 // Operands reach LDS by direct global-to-LDS loads (global_load_lds_dwordx4:
 // no staging registers) into a ring of OZ_STAGES buffers, OZ_STAGES - 1 steps
@@ -154,19 +161,20 @@ struct OzArgs {
 // c ^ oz_swz(r), so that a fragment read (sixteen rows, one chunk each) puts
 // every eight consecutive lanes on distinct 128-byte bank lines and all sixteen
 // on distinct 256-byte lines.
-constexpr int OZ_BM = 32, OZ_BN = 256, OZ_BK = 64, OZ_THREADS = 512, OZ_STAGES = 4;
+constexpr int OZ_BM = 32, OZ_BN = 256, OZ_BK = 64, OZ_THREADS = 1024, OZ_STAGES = 4;
 
 __device__ __forceinline__ int oz_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
 __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   constexpr int BM = OZ_BM, BN = OZ_BN, BK = OZ_BK, S = OZ_SLICES, NW = OZ_THREADS / 64, NS = OZ_STAGES;
+  constexpr int SH = S / 2;                      // slices per wave: the two wave halves take slices 0..3 and 4..7
   constexpr int RB = BK;                         // bytes per LDS row
   constexpr int ABYTES = S * BM * RB, STAGE = ABYTES + BN * RB;
   constexpr int QA = S * BM / 16 / NW;           // 1 KB load instructions per wave and stage
   constexpr int QB = BN / 16 / NW;
-  static_assert(BK == 64 && BM == 32 && NW == 2 * (BN / 64), "two 16-row strips x BN / 64 column strips of waves");
+  static_assert(BK == 64 && BM == 32 && NW == 4 * (BN / 64), "two row strips x BN / 64 column strips x two slice halves");
   static_assert(QA * 16 * NW == S * BM && QB * 16 * NW == BN && NS >= 2 && NS <= 5, "loader split");
-  static_assert(NS * STAGE <= 160 * 1024, "LDS");
+  static_assert(NS * STAGE <= 160 * 1024 && BM * BN * 8 <= NS * STAGE, "LDS (the ring holds the 32 x 256 partial sums at the end)");
   __shared__ __align__(1024) int8_t smem[NS * STAGE];
 
   int ti, tj;
@@ -181,10 +189,9 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   const int i0 = ti * BM, j0 = tj * BN;
   const int nk = (i0 + BM + BK - 1) / BK;   // lower triangular factor: k < i0 + BM
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wi = wave & 1, wj = wave >> 1;
+  const int wi = wave & 1, wj = (wave >> 1) & 3, wsl = wave >> 3;
   const int64_t plane = (int64_t)g.N * g.N;
 
-  // loader: instruction q of this wave fills rows 16 (q NW + wave) .. +15
   const int lrow = lane >> 2, lchunk = ((lane & 3) ^ oz_swz(lrow)) * 16;
   const int8_t* pa[QA];
   const uint8_t* pb[QB];
@@ -210,48 +217,64 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
       lds_load16(pb[q] + kt, __builtin_amdgcn_readfirstlane(base + ABYTES + 1024 * (q * NW + wave)));
   };
 
-  i4_t acc[S][4];
+  i4_t acc[SH][4];
 #pragma unroll
-  for (int s = 0; s < S; ++s)
+  for (int s = 0; s < SH; ++s)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[s][c] = i4_t{0, 0, 0, 0};
 
-  // fragment offsets: row (wi 16 + fr) of each slice, row (wj 64 + 16 c + fr) of the bytes,
-  // chunk lane >> 4 in slot chunk ^ oz_swz(fr)
   const int fr = lane & 15, slot = ((lane >> 4) ^ oz_swz(fr)) * 16;
-  const int oa = (wi * 16 + fr) * RB + slot;
+  const int oa = (wsl * SH * BM + wi * 16 + fr) * RB + slot;
   const int ob = ABYTES + (wj * 64 + fr) * RB + slot;
 
   for (int q = 0; q < NS - 1; ++q)
     if (q < nk) issue(q);
   for (int it = 0; it < nk; ++it) {
-    wait_stages<QA + QB>(min(nk - 1 - it, NS - 2));   // loads of step it have landed (this wave) ...
-    __syncthreads();                               // ... and every wave's; stage (it - 1) % NS is free
+    wait_stages<QA + QB>(min(nk - 1 - it, NS - 2));
+    __syncthreads();
     if (it + NS - 1 < nk) issue(it + NS - 1);
     const int8_t* st = smem + (it % NS) * STAGE;
     i4_t bf[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) bf[c] = *reinterpret_cast<const i4_t*>(st + ob + c * 16 * RB);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < SH; ++s) {
       const i4_t af = *reinterpret_cast<const i4_t*>(st + oa + s * BM * RB);
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[s][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[c], af, acc[s][c], 0, 0, 0);
     }
   }
 
+  // slices 7..4 (second half) first, then 3..0, the same order as one wave holding all eight
   const int i = i0 + wi * 16 + fr;
   const int e = g.ex[i];
+  double* part = reinterpret_cast<double*>(smem);   // 32 x 256 partial sums of the second half
+  wait_vmcnt<0>();
+  __syncthreads();                                  // every wave is done with the ring
+  if (wsl == 1) {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = j0 + wj * 64 + c * 16 + 4 * (lane >> 4) + t;
-      if (j >= g.ncols) continue;
-      double v = 0.0;
+      for (int t = 0; t < 4; ++t) {
+        double v = 0.0;
 #pragma unroll
-      for (int s = S - 1; s >= 0; --s) v += ldexp((double)acc[s][c][t], e - 7 * (s + 1));
-      g.C[(int64_t)i + (int64_t)j * g.ldc] = v;
+        for (int s = SH - 1; s >= 0; --s) v += ldexp((double)acc[s][c][t], e - 7 * (SH + s + 1));
+        part[(wi * 16 + fr) * BN + wj * 64 + c * 16 + 4 * (lane >> 4) + t] = v;
+      }
+  }
+  __syncthreads();
+  if (wsl == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int jl = wj * 64 + c * 16 + 4 * (lane >> 4) + t;
+        const int j = j0 + jl;
+        double v = part[(wi * 16 + fr) * BN + jl];
+#pragma unroll
+        for (int s = SH - 1; s >= 0; --s) v += ldexp((double)acc[s][c][t], e - 7 * (s + 1));
+        if (j < g.ncols) g.C[(int64_t)i + (int64_t)j * g.ldc] = v;
+      }
     }
   }
 }
