@@ -174,7 +174,8 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   constexpr int QB = BN / 16 / NW;
   static_assert(BK == 64 && BM == 32 && NW == 4 * (BN / 64), "two row strips x BN / 64 column strips x two slice halves");
   static_assert(QA * 16 * NW == S * BM && QB * 16 * NW == BN && NS >= 2 && NS <= 5, "loader split");
-  static_assert(NS * STAGE <= 160 * 1024 && BM * BN * 8 <= NS * STAGE, "LDS (the ring holds the 32 x 256 partial sums at the end)");
+  constexpr int PS = BN + 2;                     // row stride of the partial sums: 16 rows on distinct banks
+  static_assert(NS * STAGE <= 160 * 1024 && BM * PS * 8 <= NS * STAGE, "LDS (the ring holds the partial sums at the end)");
   __shared__ __align__(1024) int8_t smem[NS * STAGE];
 
   int ti, tj;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
   // slices 7..4 (second half) first, then 3..0, the same order as one wave holding all eight
   const int i = i0 + wi * 16 + fr;
   const int e = g.ex[i];
-  double* part = reinterpret_cast<double*>(smem);   // 32 x 256 partial sums of the second half
+  double* part = reinterpret_cast<double*>(smem);   // 32 x 256 partial sums of the second half (row stride PS)
   wait_vmcnt<0>();
   __syncthreads();                                  // every wave is done with the ring
   if (wsl == 1) {
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
         double v = 0.0;
 #pragma unroll
         for (int s = SH - 1; s >= 0; --s) v += ldexp((double)acc[s][c][t], e - 7 * (SH + s + 1));
-        part[(wi * 16 + fr) * BN + wj * 64 + c * 16 + 4 * (lane >> 4) + t] = v;
+        part[(wi * 16 + fr) * PS + wj * 64 + c * 16 + 4 * (lane >> 4) + t] = v;
       }
   }
   __syncthreads();
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(OZ_THREADS) void ozaki_i8_kernel(OzArgs g) {
       for (int t = 0; t < 4; ++t) {
         const int jl = wj * 64 + c * 16 + 4 * (lane >> 4) + t;
         const int j = j0 + jl;
-        double v = part[(wi * 16 + fr) * BN + jl];
+        double v = part[(wi * 16 + fr) * PS + jl];
 #pragma unroll
         for (int s = SH - 1; s >= 0; --s) v += ldexp((double)acc[s][c][t], e - 7 * (s + 1));
         if (j < g.ncols) g.C[(int64_t)i + (int64_t)j * g.ldc] = v;
