@@ -1,6 +1,8 @@
 // FP64 product C = alpha op(A) B + beta Cin for the per-block solve
-// X~ = L^-1 X and the refinement residual X - L X~: A column-major and lower
-// triangular (or full), B column-major, C column-major.  The same
+// X~ = L^-1 X and the refinement residual X - L X~ (also the setup's panel and
+// trailing products and the adjoint's L-bar update): A column-major and lower
+// triangular (or full), B column-major, C column-major, optionally only the
+// tiles that reach C's lower part.  The same
 // v_mfma_f64_4x4x4_4b_f64 accumulation as gemm_f64_kernel with the k order
 // permuted within each 16-deep stage; operands reach LDS by direct
 // global-to-LDS loads into a ring of stages.
@@ -44,6 +46,7 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
   const int Mt = g.M / BM, Nt = (g.ncols + BN - 1) / BN;
   if (!XcdMap::tile(g, blockIdx.x, Mt, Nt, &ti, &tj)) return;
   const int i0 = ti * BM, j0 = tj * BN;
+  if (g.c_lower && (i0 + BM - 1) < (j0 + g.c_diag)) return;   // a tile wholly above the lower part
   int khi = g.K;
   if (g.a_tri == TRI_LOWER) khi = imin(khi, i0 + BM + g.a_diag);
   const int nk = (khi + BK - 1) / BK;
@@ -154,13 +157,13 @@ __global__ __launch_bounds__(DB_THREADS) void trmm_f64_dma_kernel(GemmArgs g) {
 }
 
 // Whether trmm_f64_dma_kernel applies to a product without transposes: no
-// triangular B or C, 16-byte aligned operands with even leading dimensions,
+// triangular B, 16-byte aligned operands with even leading dimensions,
 // K a multiple of 16, and the rows of A up to M rounded up to 128 inside A's
 // leading dimension (they are read; rows past M are not stored).
 inline bool trmm_dma_ok(const GemmArgs& g) {
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   if (!al16(g.A) || !al16(g.B) || (g.lda & 1) || (g.ldb & 1)) return false;
-  if (g.b_tri != TRI_NONE || g.c_lower || (g.a_tri != TRI_NONE && g.a_tri != TRI_LOWER)) return false;
+  if (g.b_tri != TRI_NONE || (g.a_tri != TRI_NONE && g.a_tri != TRI_LOWER)) return false;
   if (g.a_tri == TRI_LOWER && g.a_diag != 0) return false;
   if (g.M <= 0 || g.K % DB_BK || g.K <= 0 || g.ncols <= 0 || g.mvalid > g.M) return false;
   if (g.lda < (int64_t)(g.M + DB_BM - 1) / DB_BM * DB_BM || g.ldb < g.K) return false;

@@ -104,7 +104,8 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   pl->off_L = take(sizeof(double) * N * N);
   pl->off_Linv = take(sizeof(double) * N * N);
   pl->off_W = take(sizeof(double) * N * p);
-  int64_t tmp = std::max<int64_t>(N * bc, recursion_temp_leaves(0, Kt) * NB_LEAF * NB_LEAF);
+  // the panel of a recursion node and, for big nodes, its transpose
+  int64_t tmp = std::max<int64_t>(N * bc, 2 * recursion_temp_leaves(0, Kt) * NB_LEAF * NB_LEAF);
   tmp = std::max<int64_t>(tmp, N * p * (1 + (N + TA_KC - 1) / TA_KC));   // [X_L | y] and its split-k partials
   pl->off_Xt = take(sizeof(double) * tmp);
   {
@@ -297,21 +298,47 @@ static void chol_inv_rec(Ctx* c, int a, int b, int depth, SetupSide* side, hipSt
   double* Li21 = Li + r2 + r1 * N;
   const double* Li22 = Li + r2 + r2 * N;
   double* T = c->Xt;  // w2 x w1, ld w2
-  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for((int64_t)w2 * w1)), dim3(256), 0, s, T, (int64_t)w2, A21, N, w2,
-                     w1);
-  {  // L21 = T * L11^-T   (op(B)[k][j] = Li11[j][k], non-zero for k <= j: upper)
-    GemmArgs g = gemm_args(T, w2, Li11, N, A21, N, w2, w1, w1, 1.0);
-    g.b_tri = TRI_UPPER;
-    g.b_diag = 0;
-    gemm(false, true, big_product(w2, w1), g, s);
-  }
-  {  // A22 -= L21 L21^T  (lower tiles)
-    GemmArgs g = gemm_args(A21, N, A21, N, A22, N, w2, w2, w1, -1.0);
-    g.beta = 1.0;
-    g.c_lower = 1;
-    g.c_diag = 0;
-    g.map_desc = 1;
-    gemm(false, true, big_product(w2, w2), g, s);
+  if (big_product(w2, w1)) {
+    // Both products without transposed operands, so they run on the direct-load kernel:
+    //   U = L21^T = L11^-1 A21^T (U, A21^T: w1 x w2, ld w1), L21 = U^T, A22 -= L21 U.
+    double* At = c->Xt;
+    double* U = c->Xt + (int64_t)w1 * w2;
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((w2 + 31) / 32), (unsigned)((w1 + 31) / 32)), dim3(256), 0, s,
+                       At, (int64_t)w1, A21, N, w2, w1);
+    {
+      GemmArgs g = gemm_args(Li11, N, At, w1, U, w1, w1, w2, w1, 1.0);
+      g.a_tri = TRI_LOWER;
+      g.a_diag = 0;
+      g.map_desc = 1;
+      gemm(false, false, true, g, s);
+    }
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((w1 + 31) / 32), (unsigned)((w2 + 31) / 32)), dim3(256), 0, s,
+                       A21, N, U, (int64_t)w1, w1, w2);
+    {  // lower tiles; high row tiles hold the most of them
+      GemmArgs g = gemm_args(A21, N, U, w1, A22, N, w2, w2, w1, -1.0);
+      g.beta = 1.0;
+      g.c_lower = 1;
+      g.c_diag = 0;
+      g.map_desc = 1;
+      gemm(false, false, true, g, s);
+    }
+  } else {
+    hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for((int64_t)w2 * w1)), dim3(256), 0, s, T, (int64_t)w2, A21, N, w2,
+                       w1);
+    {  // L21 = T * L11^-T   (op(B)[k][j] = Li11[j][k], non-zero for k <= j: upper)
+      GemmArgs g = gemm_args(T, w2, Li11, N, A21, N, w2, w1, w1, 1.0);
+      g.b_tri = TRI_UPPER;
+      g.b_diag = 0;
+      gemm(false, true, false, g, s);
+    }
+    {  // A22 -= L21 L21^T  (lower tiles)
+      GemmArgs g = gemm_args(A21, N, A21, N, A22, N, w2, w2, w1, -1.0);
+      g.beta = 1.0;
+      g.c_lower = 1;
+      g.c_diag = 0;
+      g.map_desc = 1;
+      gemm(false, true, big_product(w2, w2), g, s);
+    }
   }
   const bool on_side = big_product(w2, w1) && depth < 16;
   if (on_side) {   // T = L21 L11^-1 on the side stream, into this depth's region
@@ -947,7 +974,18 @@ gls_status block_backward(Ctx* c, int mb, const double* XR, int64_t ld_xr, const
   if (XR_grad)
     hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(c->n * mb)), dim3(256), 0, s, XR_grad, ld_xr, c->Xb, N, (int)c->n,
                        mb);
-  {  // Lbar -= X_R bar X~_R^T   (lower tiles; op(B)[k][j] = X~[j + k N]); high row tiles hold the most tiles
+  // Lbar -= X_R bar X~_R^T (lower tiles; high row tiles hold the most of them).  With mb a multiple of 16
+  // X~_R^T is formed in Xtb (free once X_R bar is formed) and the product runs on the direct-load kernel.
+  if (mb % 16 == 0) {
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((N + 31) / 32), (unsigned)((mb + 31) / 32)), dim3(256), 0, s,
+                       c->Xtb, (int64_t)mb, c->Xt, N, (int)N, mb);
+    GemmArgs g = gemm_args(c->Xb, N, c->Xtb, mb, c->Lbar, N, (int)N, (int)N, mb, -1.0);
+    g.beta = 1.0;
+    g.c_lower = 1;
+    g.c_diag = 0;
+    g.map_desc = 1;
+    gemm(false, false, true, g, s);
+  } else {  // op(B)[k][j] = X~[j + k N]
     GemmArgs g = gemm_args(c->Xb, N, c->Xt, N, c->Lbar, N, (int)N, (int)N, mb, -1.0);
     g.beta = 1.0;
     g.c_lower = 1;

@@ -46,6 +46,30 @@ __global__ void copy2d_kernel(double* __restrict__ dst, int64_t ld_dst,
   }
 }
 
+// dst (cols x rows, ld_dst) <- src^T for src (rows x cols, ld_src), through
+// 32 x 32 LDS tiles so that both the reads and the writes are column runs.
+__global__ __launch_bounds__(256) void transpose_kernel(double* __restrict__ dst, int64_t ld_dst,
+                                                        const double* __restrict__ src, int64_t ld_src, int rows,
+                                                        int cols) {
+  __shared__ double tile[32][33];
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  double v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + tx, c = c0 + ty + 8 * q;
+    v[q] = (r < rows && c < cols) ? src[(int64_t)r + (int64_t)c * ld_src] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) tile[ty + 8 * q][tx] = v[q];   // tile[c - c0][r - r0]
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + tx, r = r0 + ty + 8 * q;               // dst row c, column r
+    if (r < rows && c < cols) dst[(int64_t)c + (int64_t)r * ld_dst] = tile[tx][ty + 8 * q];
+  }
+}
+
 // Wpack (N x p, ld N) <- [X_L | y] with zero rows n..N-1.
 __global__ void pack_covariates_kernel(double* __restrict__ Wp, int N, int n, int p,
                                        const double* __restrict__ XL, int64_t ld_xl,
