@@ -497,7 +497,8 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
 
   hipError_t e;
   int hinfo[2] = {0, 0};
-  auto fail = [&](gls_status st) {
+  auto fail = [&](gls_status st) {   // nothing enqueued here may still run on the caller's workspace
+    (void)hipStreamSynchronize(s);
     delete c;
     return st;
   };
@@ -511,10 +512,7 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
       return fail(hip_fail(e, "gls_setup: side stream"));
     chol_inv_rec(c, 0, (int)(N / NB_LEAF), 0, &side, s);
     // every side product is joined into s by its node's last product
-    if (side.err != hipSuccess) {
-      (void)hipStreamSynchronize(s);
-      return fail(hip_fail(side.err, "gls_setup: side stream fork/join"));
-    }
+    if (side.err != hipSuccess) return fail(hip_fail(side.err, "gls_setup: side stream fork/join"));
   }
   c->ub[0] = reinterpret_cast<uint8_t*>(ws + pl.off_ub0);
   c->ub[1] = reinterpret_cast<uint8_t*>(ws + pl.off_ub1);

@@ -101,9 +101,9 @@ std::vector<int64_t> block_schedule(int64_t bc, int64_t total) {
 }  // namespace
 
 template <typename T>
-static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR_host, int64_t ld_xr, double* b_host,
-                              double* sigma2_host, double* v_host, int32_t* status_host, void* compute_stream,
-                              void* copy_stream, gls_stream_stats* stats_out) {
+static gls_status stream_run(gls_handle h, int64_t m, int64_t col0, const T* XR_host, int64_t ld_xr, double* b_host,
+                             double* sigma2_host, double* v_host, int32_t* status_host, void* compute_stream,
+                             void* copy_stream, gls_stream_stats* stats_out) {
   Ctx* c = h;
   if (!c || !c->ready) return arg_fail("gls_stream: handle is not set up"), GLS_ERR_STATE;
   if (m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream: need 0 <= col0 <= m");
@@ -196,6 +196,21 @@ static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR
   st.blocks = nblk;
   if (stats_out) *stats_out = st;
   return GLS_OK;
+}
+
+// A failed stream drains both streams before returning, so that no copy into
+// the caller's host buffers is still in flight.
+template <typename T>
+static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR_host, int64_t ld_xr, double* b_host,
+                              double* sigma2_host, double* v_host, int32_t* status_host, void* compute_stream,
+                              void* copy_stream, gls_stream_stats* stats_out) {
+  const gls_status r = stream_run(h, m, col0, XR_host, ld_xr, b_host, sigma2_host, v_host, status_host,
+                                  compute_stream, copy_stream, stats_out);
+  if (r != GLS_OK) {
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(compute_stream));
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(copy_stream));
+  }
+  return r;
 }
 
 extern "C" gls_status gls_stream(gls_handle h, int64_t m, int64_t col0, const double* XR_host, int64_t ld_xr,
