@@ -328,7 +328,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build "
+        print("bench.py: the solver runs on one GPU; runs on several GPUs are not supported "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE={world})", file=sys.stderr)
         sys.exit(2)
 
