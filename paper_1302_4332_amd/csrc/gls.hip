@@ -65,8 +65,8 @@ static int64_t recursion_temp_leaves(int a, int b) {
 }
 
 // Setup products of at least this many output elements use the XCD-aware
-// mapping, and the inverse factor's T = L21 L11^-1 of such a node runs on
-// the side stream.
+// mapping; a node whose panel is this big forms its panel products on the
+// direct-load kernel and runs its T = L21 L11^-1 on the side stream.
 static bool big_product(int64_t rows, int64_t cols) { return rows * cols >= (int64_t)1024 * 1024; }
 
 // Per recursion depth, the largest (b - mid) x (mid - a) leaf product of a
