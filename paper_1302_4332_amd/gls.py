@@ -295,6 +295,8 @@ class GLSContext:
         """
         _need(XR_host, "XR_host", XR_host.dtype if XR_host.dtype in (torch.uint8, torch.float64) else torch.float64,
               cuda=False)
+        if XR_host.is_cuda:
+            raise TypeError("XR_host must be a host tensor (page-locked: .pin_memory())")
         if packed:
             _need(XR_host, "XR_host", torch.uint8, cuda=False)
             entry, rowlen = lib().gls_stream_u2, (self.n + 3) // 4
