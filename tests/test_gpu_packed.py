@@ -144,3 +144,27 @@ def test_u2_argument_errors():
     assert st == -1                                    # mb > block_cols
     assert lib().gls_stream_file_host_bytes(ctx.handle, 4) == 0
     assert lib().gls_stream_file_host_bytes(ctx.handle, 2) == 3 * 4096
+
+
+def test_u2_no_covariates_and_stream_resume():
+    """p = 1 (the SNP alone) with int8 slices from packed dosages, and a packed
+    stream resumed at col0: the columns before it untouched, the rest equal to
+    the full stream."""
+    n, m = 301, 500
+    Phi = synth.kinship(n, 9)
+    y = synth.phenotype(n, 9)
+    G = synth.genotypes_u8(n, 0, m, 9)
+    P = synth.pack_dosages_2bit(G)
+    ctx = GLSContext(_t(Phi), 0.5, None, _t(y), block_cols=128, precision="int8_emu")
+    a = _run_u8(ctx, G, 128)
+    b = _collect([ctx.block_u2(_t(P[j:j + 128])) for j in range(0, m, 128)])
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    Ph = torch.tensor(P).pin_memory()
+    (full, *_), _ = ctx.stream(Ph, packed=True)
+    f = torch.float64
+    out = (torch.full((m, 1), -7.0, dtype=f).pin_memory(), torch.zeros(m, dtype=f).pin_memory(),
+           torch.zeros(m, dtype=f).pin_memory(), torch.zeros(m, dtype=torch.int32).pin_memory())
+    (part, *_), stats = ctx.stream(Ph, col0=333, out=out, packed=True)
+    assert stats.h2d_bytes == ((n + 3) // 4) * (m - 333)
+    assert (part.numpy()[:333] == -7.0).all() and np.array_equal(part.numpy()[333:], full.numpy()[333:])
