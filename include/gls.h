@@ -166,7 +166,8 @@ typedef struct {
  * first copy, which nothing overlaps, is short; results are bitwise the same
  * for any blocking.
  * Returns after every result has landed.  col0 > 0 resumes an interrupted
- * run: outputs for columns < col0 are not touched. */
+ * run: outputs for columns < col0 are not touched.  col0 == m (an empty
+ * stream) returns GLS_OK at once, and the pointers may then be NULL. */
 gls_status gls_stream(gls_handle h, int64_t m, int64_t col0,
                       const double* XR_host, int64_t ld_xr,
                       double* b_host, double* sigma2_host, double* v_host,

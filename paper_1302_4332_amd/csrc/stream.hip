@@ -107,6 +107,10 @@ static gls_status stream_run(gls_handle h, int64_t m, int64_t col0, const T* XR_
   Ctx* c = h;
   if (!c || !c->ready) return arg_fail("gls_stream: handle is not set up"), GLS_ERR_STATE;
   if (m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream: need 0 <= col0 <= m");
+  if (col0 == m) {   // nothing to stream: no pointer is used
+    if (stats_out) *stats_out = gls_stream_stats{};
+    return GLS_OK;
+  }
   const int64_t rows = col_elems(c, XR_host);
   if (!XR_host || ld_xr < rows) return arg_fail("gls_stream: the SNP matrix is NULL or its ld is below a column");
   if (!b_host || !sigma2_host || !v_host || !status_host) return arg_fail("gls_stream: NULL host output");
@@ -457,6 +461,10 @@ extern "C" gls_status gls_stream_file(gls_handle h, const char* path, int64_t of
   if (!c || !c->ready) return arg_fail("gls_stream_file: handle is not set up"), GLS_ERR_STATE;
   if (!path || offset < 0 || m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream_file: bad path/offset/m/col0");
   if (file_col_bytes(c, elem_bits) == 0) return arg_fail("gls_stream_file: elem_bits must be 64, 8 or 2");
+  if (col0 == m) {   // nothing to read: neither the file nor any buffer is used
+    if (stats_out) *stats_out = gls_stream_stats{};
+    return GLS_OK;
+  }
   if (!host_ws || host_ws_bytes < host_ring_bytes(c, file_col_bytes(c, elem_bits)))
     return arg_fail("gls_stream_file: host_ws smaller than gls_stream_file_host_bytes()");
   if (!b_host || !sigma2_host || !v_host || !status_host) return arg_fail("gls_stream_file: NULL host output");

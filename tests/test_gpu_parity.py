@@ -190,3 +190,16 @@ def test_stream_ramp_bitwise():
     (b2, _, _, st2), stats2 = ctx.stream(host, col0=300)
     assert stats2.blocks == _ramp_blocks(9000, 300, bc)
     assert np.array_equal(b2.numpy()[300:], ref["b"][300:]) and np.array_equal(st2.numpy()[300:], ref["status"][300:])
+
+
+def test_empty_inputs():
+    """Empty blocks and streams are no-ops: mb = 0, m = 0 and col0 = m."""
+    Phi, h2, XL, y, XR = _problem(260, 4, 5, seed=31)
+    ctx = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=16)
+    b, s2, v, st = ctx.block(_t(XR[:0]))
+    assert b.shape == (0, 4) and s2.shape == (0,)
+    (bs, *_), stats = ctx.stream(torch.empty((0, 260), dtype=torch.float64).pin_memory())
+    assert stats.blocks == 0 and stats.h2d_bytes == 0 and bs.shape == (0, 4)
+    host = torch.tensor(XR).pin_memory()
+    (bs, *_), stats = ctx.stream(host, col0=5)
+    assert stats.blocks == 0 and np.isnan(bs.numpy()).all()
