@@ -33,6 +33,8 @@ def test_workspace_planning():
     assert gls.workspace_bytes(10, 10, o) == 0          # n <= p
     assert gls.workspace_bytes(100, 0, o) == 0          # p < 1
     assert gls.workspace_bytes(100, 21, o) == 0         # p > 20
+    assert gls.workspace_bytes(2 ** 20 + 1, 4, o) == 0  # n above the supported 2^20
+    assert gls.workspace_bytes(100, 20, o) > 0          # p = 20, the largest supported
     assert gls.workspace_bytes(100, 4, gls.make_opts(0)) == 0
     assert gls.workspace_bytes(100, 4, gls.make_opts(16, refine_sweeps=9)) == 0
     small = gls.workspace_bytes(512, 4, gls.make_opts(64))
