@@ -85,7 +85,8 @@ typedef struct {
 } gls_opts;
 
 /* Device workspace (bytes) a handle with these sizes and options needs.
- * Returns 0 for invalid arguments (n <= p, p < 1, p > 20, block_cols < 1). */
+ * Returns 0 for invalid arguments (n <= p, n > 2^20, p < 1, p > 20,
+ * block_cols < 1, refine_sweeps outside 0..4, unknown precision). */
 size_t gls_workspace_bytes(int64_t n, int32_t p, const gls_opts* opts);
 
 /* Study setup (Sec. 2.1, Listing 1 before the SNP loop; Eq. 2):
