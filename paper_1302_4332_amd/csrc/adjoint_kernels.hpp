@@ -273,6 +273,41 @@ __global__ void wbar_shared_kernel(const double* __restrict__ W, const double* _
 
 // A (N x N): zero above the diagonal; with halve_diag also halve the diagonal
 // (the operator that keeps the lower triangle and half the diagonal).
+// W (N x P, ld N) = L^-T V for V (N x P, ld N) and the lower-triangular
+// inverse factor Li (N x N, ld N): row i of the result needs column i of Li
+// from row i down, a contiguous run.  One wave per output row, lanes over k
+// (four loads in flight per lane), then a fixed-order wave reduction per
+// column of V.
+template <int P>
+__global__ __launch_bounds__(256) void tri_apply_t_kernel(const double* __restrict__ Li, int N,
+                                                          const double* __restrict__ V, double* __restrict__ W) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= N) return;
+  const double* col = Li + (int64_t)i * N;
+  double acc[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) acc[j] = 0.0;
+  for (int kb = i + lane; kb < N; kb += 256) {
+    double a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = (kb + 64 * u < N) ? col[kb + 64 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = kb + 64 * u;
+      if (k < N) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[j] = fma(a[u], V[k + (int64_t)j * N], acc[j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const double t = wave_sum(acc[j]);
+    if (lane == 0) W[i + (int64_t)j * N] = t;
+  }
+}
+
 __global__ void lower_part_kernel(double* __restrict__ A, int N, int halve_diag) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)N * N;

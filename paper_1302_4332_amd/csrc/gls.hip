@@ -1001,12 +1001,11 @@ gls_status finish_backward(Ctx* c, double* y_grad, double* h2_grad, hipStream_t 
 #define GLS_WB(P) wbar_shared_p<P>(c, s)
   GLS_P_SWITCH(p, GLS_WB)
 #undef GLS_WB
-  {  // [X_L | y] bar = L^-T [X~_L | y~] bar
-    GemmArgs g = gemm_args(c->Linv, N, c->Wb, N, c->W0b, N, (int)N, p, (int)N, 1.0);
-    g.a_tri = TRI_UPPER;
-    g.a_diag = 0;
-    gemm(true, false, false, g, s);
-  }
+  // [X_L | y] bar = L^-T [X~_L | y~] bar
+#define GLS_TT(P) \
+  hipLaunchKernelGGL(tri_apply_t_kernel<P>, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, c->Linv, (int)N, c->Wb, c->W0b);
+  GLS_P_SWITCH(p, GLS_TT)
+#undef GLS_TT
   if (y_grad)
     hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(c->n)), dim3(256), 0, s, y_grad, c->n, c->W0b + (int64_t)(p - 1) * N,
                        N, (int)c->n, 1);
