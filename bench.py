@@ -1,11 +1,15 @@
 #!/usr/bin/env python3
 """Throughput of the streamed GWAS GLS hot path on one MI355X.
 
-One step = one whole study: setup (M, Cholesky, inverse factor, covariate
-terms), every SNP block through the triangular product, the per-SNP products
-and p x p solves, and the results copied to host memory.  The SNP matrix is
-resident in HBM when the timed region starts (the PCIe-inclusive streamed
-rate is reported separately with --stream).  Prints one JSON line.
+One step = one whole study streamed from page-locked host memory (the
+paper's setting, Sec. 3.1): every SNP block copied to the device through the
+double-buffered pipeline, the triangular product, the per-SNP products and
+p x p solves, and the results copied back into host arrays, from the first
+copy to the last result landed.  The setup (M, Cholesky, inverse factor,
+covariate terms) runs once before the steps and is reported separately
+(setup_ms), as the paper times it apart.  The value is m over the median
+step time.  The whole study with the SNP matrix resident in HBM, setup
+included, is reported as hbm_resident.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload c1_n10k_m100k]
 """
@@ -305,10 +309,98 @@ def measure_scale(args, dev):
     return res
 
 
+def measure_resident(args, Phi_d, XL_d, y_d, X_d, m, n, p, bc, h2, steps):
+    """The whole study with the SNP matrix already in HBM, setup included:
+    setup, every block, results copied to host memory."""
+    import torch
+
+    from paper_1302_4332_amd.gls import GLSContext
+
+    dev = X_d.device
+    b_d = torch.empty((m, p), dtype=torch.float64, device=dev)
+    s2_d = torch.empty(m, dtype=torch.float64, device=dev)
+    v_d = torch.empty(m, dtype=torch.float64, device=dev)
+    st_d = torch.empty(m, dtype=torch.int32, device=dev)
+    b_h = torch.empty((m, p), dtype=torch.float64).pin_memory()
+
+    def study():
+        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps)
+        for j0 in range(0, m, bc):
+            j1 = min(m, j0 + bc)
+            ctx.block_into(X_d[j0:j1], b_d[j0:j1], s2_d[j0:j1], v_d[j0:j1], st_d[j0:j1])
+        b_h.copy_(b_d, non_blocking=True)
+        ctx.close()
+
+    study()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        study()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    log(f"HBM-resident whole study incl. setup: {ms:.1f} ms -> {m / (ms / 1e3):,.0f} SNPs/s")
+    return {"snps_per_s": m / (ms / 1e3), "ms_per_study": ms, "studies": steps,
+            "note": "SNP matrix resident in HBM; setup, every block and the results' copy to host timed"}
+
+
+def cpu_baselines(args, st, m, bc, h2, g_b, g_status):
+    """The oracle on the host: the whole study on every BLAS thread (or a
+    sample, --cpu-sample), and a bounded sample on one thread; both check this
+    run's streamed outputs on the SNPs they solve."""
+    from oracle import gls_oracle as O
+
+    S = m if args.cpu_sample <= 0 else min(args.cpu_sample, m)
+    log(f"cpu baseline: oracle setup + {S} SNPs on the host, in blocks of {bc}")
+    t = time.perf_counter()
+    ost = O.Study(st.Phi, h2, st.XL, st.y)
+    t_setup = time.perf_counter() - t
+    t_blk, err, status_equal = 0.0, 0.0, True
+
+    def check(j0, j1, study):
+        nonlocal err, status_equal
+        XRs = st.snps(j0, j1)                  # drawing the inputs is not timed
+        t = time.perf_counter()
+        ref = study.block(XRs.T)
+        dt = time.perf_counter() - t
+        ok = ref["status"] == 0
+        e = np.max(np.abs(g_b[j0:j1][ok] - ref["b"][ok]), axis=1) / np.max(np.abs(ref["b"][ok]), axis=1)
+        err = max(err, float(e.max()) if e.size else 0.0)
+        status_equal = status_equal and bool(np.array_equal(g_status[j0:j1], ref["status"]))
+        return dt
+
+    for j0 in range(0, S, bc):
+        t_blk += check(j0, min(S, j0 + bc), ost)
+    if S < m:
+        check(m - 64, m, ost)                   # and the study's ragged tail
+    cpu_total = t_setup + (m / S) * t_blk
+    whole = "the whole study" if S == m else "whole-study time extrapolated linearly in m"
+    res = {"value": m / cpu_total, "unit": "SNPs/s", "cores": blas_threads(), "kind": "oracle",
+           "sample": f"oracle setup (Cholesky of M, covariate terms) {t_setup:.1f}s + SNPs "
+                     f"[0,{S}) in blocks of {bc} {t_blk:.1f}s; {whole}",
+           "host": host_info()}
+    parity = {"snps": int(S + (64 if S < m else 0)), "max_rel_err_b": err, "status_equal": status_equal,
+              "outputs": "the streamed outputs of the last timed step"}
+    log(f"cpu baseline {res['value']:,.0f} SNPs/s; max rel err of b over {S} SNPs {err:.2e}")
+    if args.cpu_single_sample > 0:
+        import threadpoolctl
+        S1 = min(args.cpu_single_sample, m)
+        with threadpoolctl.threadpool_limits(1):
+            t = time.perf_counter()
+            ost1 = O.Study(st.Phi, h2, st.XL, st.y)
+            t1_setup = time.perf_counter() - t
+            t1_blk = check(0, S1, ost1)
+        total1 = t1_setup + (m / S1) * t1_blk
+        res["single_thread"] = {"value": m / total1, "unit": "SNPs/s", "cores": 1,
+                                "sample": f"oracle setup {t1_setup:.1f}s + SNPs [0,{S1}) {t1_blk:.1f}s on one "
+                                          f"thread; whole-study time extrapolated linearly in m"}
+        log(f"cpu baseline, one thread: {m / total1:,.0f} SNPs/s")
+    return res, parity
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1_n10k_m100k")
     ap.add_argument("--m", type=int, default=None, help="override the SNP count")
@@ -317,7 +409,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="SNPs the oracle solves for the CPU baseline (0: the whole study)")
-    ap.add_argument("--no-stream", action="store_true", help="skip the streamed (pinned host memory) measurement")
+    ap.add_argument("--cpu-single-sample", type=int, default=2048,
+                    help="SNPs the one-thread oracle run solves (0: skip it)")
+    ap.add_argument("--resident-steps", type=int, default=2,
+                    help="whole studies timed with the SNP matrix resident in HBM (0: skip)")
+    ap.add_argument("--no-serial", action="store_true", help="skip the no-overlap ablation")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision and adjoint measurements")
     ap.add_argument("--no-bytes", action="store_true", help="skip the genotype-byte and packed-dosage measurements")
     ap.add_argument("--scale", default=None,
@@ -348,14 +444,13 @@ def main():
     Phi_d = torch.tensor(st.Phi, device=dev)
     XL_d = torch.tensor(st.XL, device=dev)
     y_d = torch.tensor(st.y, device=dev)
-    X_d = torch.empty((m, n), dtype=torch.float64, device=dev)
+    host = torch.empty((m, n), dtype=torch.float64).pin_memory()
     CH = 16384
     t = time.perf_counter()
     for j0 in range(0, m, CH):
         j1 = min(m, j0 + CH)
-        X_d[j0:j1] = torch.from_numpy(synth.genotypes_u8(n, j0, j1, w.seed)).to(dev).to(torch.float64)
-    torch.cuda.synchronize()
-    log(f"SNP matrix resident in HBM ({X_d.numel() * 8 / 1e9:.1f} GB) after {time.perf_counter() - t:.1f}s")
+        host[j0:j1] = torch.from_numpy(synth.genotypes_u8(n, j0, j1, w.seed)).to(torch.float64)
+    log(f"SNP matrix in page-locked host memory ({host.numel() * 8 / 1e9:.1f} GB) after {time.perf_counter() - t:.1f}s")
 
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -365,59 +460,50 @@ def main():
         del src, dst
         log("calibration copy of 1 GiB done")
 
-    b_d = torch.empty((m, p), dtype=torch.float64, device=dev)
-    s2_d = torch.empty(m, dtype=torch.float64, device=dev)
-    v_d = torch.empty(m, dtype=torch.float64, device=dev)
-    st_d = torch.empty(m, dtype=torch.int32, device=dev)
-    b_h = torch.empty((m, p), dtype=torch.float64).pin_memory()
-    s2_h = torch.empty(m, dtype=torch.float64).pin_memory()
-    v_h = torch.empty(m, dtype=torch.float64).pin_memory()
-    st_h = torch.empty(m, dtype=torch.int32).pin_memory()
-    phase_tot = {}
-
-    def step(profile: bool):
-        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision,
-                         refine_sweeps=args.sweeps)
-        if profile:
-            ctx.profile(True)
-        for j0 in range(0, m, bc):
-            j1 = min(m, j0 + bc)
-            ctx.block_into(X_d[j0:j1], b_d[j0:j1], s2_d[j0:j1], v_d[j0:j1], st_d[j0:j1])
-        b_h.copy_(b_d, non_blocking=True)
-        s2_h.copy_(s2_d, non_blocking=True)
-        v_h.copy_(v_d, non_blocking=True)
-        st_h.copy_(st_d, non_blocking=True)
-        if profile:
-            for k, (cnt, ms) in ctx.profile_read().items():
-                c0, m0 = phase_tot.get(k, (0, 0.0))
-                phase_tot[k] = (c0 + cnt, m0 + ms)
-        ctx.close()
-
-    for i in range(args.warmup):
-        step(False)
+    # setup alone (M, Cholesky, inverse factor, covariate terms): median of three
+    setups = []
+    for _ in range(3):
         torch.cuda.synchronize()
+        ts = time.perf_counter()
+        GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps).close()
+        torch.cuda.synchronize()
+        setups.append((time.perf_counter() - ts) * 1e3)
+    setup_ms = float(np.median(setups))
+    log(f"setup {setup_ms:.1f} ms (median of 3)")
+
+    # the headline: the study streamed from page-locked host memory through the
+    # double-buffered pipeline, first copy to last result in host memory
+    ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps)
+    out_h = (torch.empty((m, p), dtype=torch.float64).pin_memory(), torch.empty(m, dtype=torch.float64).pin_memory(),
+             torch.empty(m, dtype=torch.float64).pin_memory(), torch.empty(m, dtype=torch.int32).pin_memory())
+    for i in range(args.warmup):
+        ctx.stream(host, out=out_h)
         log(f"warmup step {i + 1}/{args.warmup} done")
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    step_ms, dev_wall, h2d = [], [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(True)
-        log(f"timed step {i + 1}/{args.steps} enqueued")
+        ts = time.perf_counter()
+        _, stats = ctx.stream(host, out=out_h)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        dev_wall.append(stats.wall_ms)
+        h2d += stats.h2d_bytes
+        log(f"timed step {i + 1}/{args.steps}: {step_ms[-1]:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = m / (ms_per_step / 1e3)
-    log(f"{ms_per_step:.1f} ms/step -> {value:,.0f} SNPs/s")
+    phases = ctx.profile_read(reset=True)
+    blocks = stats.blocks
+    ctx.close()
+    mean_ms = (t1 - t0) * 1e3 / args.steps
+    med_ms = float(np.median(step_ms))
+    value = m / (med_ms / 1e3)
+    log(f"streamed: median {med_ms:.1f} ms/step -> {value:,.0f} SNPs/s (mean {mean_ms:.1f} ms)")
 
-    # setup-only time (excluded from nothing above; reported for context)
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps).close()
-    torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - ts) * 1e3
-
-    wl, wms = phase_tot.get("whiten", (0, 0.0))
-    flops_per_step = float(n) * n * m
-    achieved = flops_per_step * args.steps / (wms / 1e3) / 1e12 if wms > 0 else None
+    wl, wms = phases["whiten"]
+    flops = float(n) * n * m * args.steps
+    achieved = flops / (wms / 1e3) / 1e12 if wms > 0 else None
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
     if (args.precision == "fp64" and kernel_hash() == TRAFFIC_RECORD["kernel_sha1"] and n == TRAFFIC_RECORD["n"]
@@ -428,85 +514,50 @@ def main():
                 "traffic_unit": "bytes per full 8,192-SNP launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE, calibrated)",
                 "kernel": "trmm_f64_dma_kernel (X~ = L^-1 X; 128 x 64 tiles, v_mfma_f64_4x4x4_4b_f64)",
                 "launch_ms_avg": wms / wl if wl else None, "launches": wl,
-                "flops_per_snp": float(n) * n}
+                "flops_per_snp": float(n) * n,
+                "timing": "HIP events around each launch on the compute stream, over the timed streamed steps"}
     out = {
         "metric": METRIC, "value": value, "unit": "SNPs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": med_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else args.precision, "data": "synthetic",
         "config": {"workload": w.name, "n": n, "p": p, "m": m, "block_cols": bc, "h2": h2,
-                   "precision": args.precision, "refine_sweeps": args.sweeps, "inputs": "HBM-resident"},
+                   "precision": args.precision, "refine_sweeps": args.sweeps,
+                   "inputs": "pinned-host, streamed", "setup": "excluded (reported as setup_ms)"},
         "roofline": roofline,
-        "phases_ms_per_step": {k: v[1] / args.steps for k, v in phase_tot.items()},
-        "setup_ms": setup_ms,
-        "snps_per_s_excl_setup": m / ((ms_per_step - setup_ms) / 1e3) if ms_per_step > setup_ms else None,
+        "step_ms": step_ms, "ms_per_step_mean": mean_ms, "step_statistic": "median",
+        "device_wall_ms": dev_wall, "h2d_GBps": h2d / (sum(step_ms) / 1e3) / 1e9, "stream_blocks": blocks,
+        "phases_ms_per_step": {k: v[1] / args.steps for k, v in phases.items()},
+        "setup_ms": setup_ms, "setup_ms_samples": setups,
+        "snps_per_s_incl_setup": m / ((med_ms + setup_ms) / 1e3),
         "device_memory": {"peak_allocated_bytes": int(torch.cuda.max_memory_allocated()),
-                          "workspace_bytes": workspace_bytes(n, p, make_opts(bc, args.precision, args.sweeps)),
-                          "snp_matrix_bytes": int(X_d.numel() * 8)},
+                          "workspace_bytes": workspace_bytes(n, p, make_opts(bc, args.precision, args.sweeps))},
     }
+    if not args.no_serial:
+        sctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps,
+                          serial_stream=True)
+        _, ss = sctx.stream(host)
+        sctx.close()
+        out["serial_stream"] = {"snps_per_s": m / (ss.wall_ms / 1e3), "wall_ms": ss.wall_ms,
+                                "note": "no-overlap ablation: copy, solve and results one after another"}
+        log(f"serial stream: {m / (ss.wall_ms / 1e3):,.0f} SNPs/s")
 
+    need_resident = args.resident_steps > 0 or not args.no_forms or not args.no_bytes
+    X_d = None
+    if need_resident:
+        X_d = host.to(dev)
+        if args.resident_steps > 0:
+            out["hbm_resident"] = measure_resident(args, Phi_d, XL_d, y_d, X_d, m, n, p, bc, h2, args.resident_steps)
     if not args.no_forms:
         out["forms"] = measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev)
     if not args.no_bytes:
-        out["bytes"] = measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_h)
-    if not args.no_stream:
-        host = torch.empty((m, n), dtype=torch.float64).pin_memory()
-        host.copy_(X_d)
-        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps)
-        ctx.stream(host)
-        torch.cuda.synchronize()
-        (_, _, _, _), stats = ctx.stream(host)
-        out["stream"] = {"snps_per_s": m / (stats.wall_ms / 1e3), "wall_ms": stats.wall_ms,
-                         "compute_ms": stats.compute_ms, "h2d_GBps": stats.h2d_bytes / (stats.wall_ms / 1e3) / 1e9,
-                         "blocks": stats.blocks, "note": "PCIe-inclusive: pinned host X_R, setup excluded"}
-        ctx.close()
-        ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps,
-                         serial_stream=True)
-        (_, _, _, _), ss = ctx.stream(host)
-        out["stream"]["serial_snps_per_s"] = m / (ss.wall_ms / 1e3)
-        out["stream"]["serial_wall_ms"] = ss.wall_ms
-        ctx.close()
-        del host
-        log(f"streamed: {out['stream']['snps_per_s']:,.0f} SNPs/s")
-
+        out["bytes"] = measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, out_h[0])
+    del X_d
     if args.scale:
         out["scale"] = measure_scale(args, dev)
 
     if not args.no_cpu_baseline:
-        from oracle import gls_oracle as O
-        S = m if args.cpu_sample <= 0 else min(args.cpu_sample, m)
-        log(f"cpu baseline: oracle setup + {S} SNPs on the host, in blocks of {bc}")
-        t = time.perf_counter()
-        ost = O.Study(st.Phi, h2, st.XL, st.y)
-        t_setup = time.perf_counter() - t
-        g, gst = b_h.numpy(), st_h.numpy()
-        t_blk, err, status_equal = 0.0, 0.0, True
-
-        def check(j0, j1):
-            nonlocal t_blk, err, status_equal
-            XRs = st.snps(j0, j1)                  # drawing the inputs is not timed
-            t = time.perf_counter()
-            ref = ost.block(XRs.T)
-            dt = time.perf_counter() - t
-            ok = ref["status"] == 0
-            e = np.max(np.abs(g[j0:j1][ok] - ref["b"][ok]), axis=1) / np.max(np.abs(ref["b"][ok]), axis=1)
-            err = max(err, float(e.max()) if e.size else 0.0)
-            status_equal = status_equal and bool(np.array_equal(gst[j0:j1], ref["status"]))
-            return dt
-
-        for j0 in range(0, S, bc):
-            t_blk += check(j0, min(S, j0 + bc))
-        if S < m:
-            check(m - 64, m)                        # and the study's ragged tail
-        cpu_total = t_setup + (m / S) * t_blk
-        whole = "the whole study" if S == m else "whole-study time extrapolated linearly in m"
-        out["cpu_baseline"] = {"value": m / cpu_total, "unit": "SNPs/s", "cores": blas_threads(), "kind": "oracle",
-                               "sample": f"oracle setup (Cholesky of M, covariate terms) {t_setup:.1f}s + SNPs "
-                                         f"[0,{S}) in blocks of {bc} {t_blk:.1f}s; {whole}",
-                               "host": host_info()}
-        # parity of this run's outputs against the oracle on the same SNPs
-        out["parity_vs_oracle"] = {"snps": int(S + (64 if S < m else 0)), "max_rel_err_b": err,
-                                   "status_equal": status_equal}
-        log(f"cpu baseline {out['cpu_baseline']['value']:,.0f} SNPs/s; max rel err of b over {S} SNPs {err:.2e}")
+        out["cpu_baseline"], out["parity_vs_oracle"] = cpu_baselines(args, st, m, bc, h2, out_h[0].numpy(),
+                                                                     out_h[3].numpy())
     print(json.dumps(out), flush=True)
 
 

@@ -28,8 +28,14 @@
  *   - Pointers are DEVICE pointers unless the name ends in _host.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *   - The caller owns every input, output and the workspace.  The library
- *     never allocates device memory; it only allocates its small handle and
- *     creates HIP events (freed by gls_destroy).
+ *     never allocates device memory.  Host-side resources: the small handle
+ *     and its HIP events (freed by gls_destroy); gls_setup also creates a
+ *     side stream and events of its own, which it synchronizes and destroys
+ *     before returning; gls_stream_file runs a reader thread that is joined
+ *     before the call returns.
+ *   - Work the library enqueues on a caller's stream reads and writes the
+ *     workspace asynchronously: the workspace must not be freed or reused
+ *     until that stream has finished it.
  *   - Every call returns a gls_status; no C++ exception crosses the ABI.
  *     gls_last_error() gives a thread-local message for the last failure.
  */

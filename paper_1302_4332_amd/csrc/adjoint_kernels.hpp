@@ -28,7 +28,7 @@ __host__ __device__ constexpr int adj_nc(int p) { return (p - 1) * p / 2 + (p - 
 
 template <int P>
 __global__ __launch_bounds__(64 * SNP_WAVES)
-void snp_adjoint_kernel(const double* __restrict__ Xt, int64_t ldx, int N, int mb, const double* __restrict__ W,
+void snp_adjoint_kernel(double* __restrict__ Xt, int64_t ldx, int N, int mb, const double* __restrict__ W,
                         const double* __restrict__ small, int n, const double* __restrict__ bbar, int64_t ldbb,
                         const double* __restrict__ s2bar, const double* __restrict__ vbar,
                         double* __restrict__ Cbar, double* __restrict__ ebar, double* __restrict__ contrib) {
@@ -94,11 +94,17 @@ void snp_adjoint_kernel(const double* __restrict__ Xt, int64_t ldx, int N, int m
     lz += l[j] * zT[j];
   }
   const double bb_p = bbar[(int64_t)c * ldbb + (P - 1)];
-  if (!(d2 > SINGULAR_REL * sbr)) {   // singular S_i: no contribution
+  if (!(d2 > SINGULAR_REL * sbr)) {
+    // singular S_i (status 1, NaN outputs): no contribution.  Its whitened
+    // column may hold NaN (a NaN sample), and 0 * NaN would reach the
+    // study-wide sums through the later products with X~, so the column is
+    // zeroed; the wave's reads of it are complete (they fed the sums above).
 #pragma unroll
     for (int j = 0; j < P; ++j) cb[j] = 0.0;
     ebar[c] = 0.0;
     for (int t = 0; t < NC; ++t) ct[t] = 0.0;
+    double* col = Xt + (int64_t)c * ldx;
+    for (int r = 0; r < N; ++r) col[r] = 0.0;
     return;
   }
   const double d = sqrt(d2);

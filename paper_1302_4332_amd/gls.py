@@ -178,6 +178,18 @@ class GLSContext:
         _check(st, info.value)
         self.handle = h
         self.block_cols = block_cols
+        self._streams = set()
+
+    def _use(self, stream):
+        """The stream the library will enqueue on; a stream other than the one the
+        workspace was allocated on is recorded with the caching allocator, so the
+        workspace is not handed out again while work queued there may still run."""
+        s = torch.cuda.current_stream() if stream is None else stream
+        key = s.cuda_stream
+        if key not in self._streams:
+            self._streams.add(key)
+            self.workspace.record_stream(s)
+        return ctypes.c_void_p(key)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -211,7 +223,7 @@ class GLSContext:
             if t.shape[0] != mb or (name == "b" and tuple(t.shape) != (mb, self.p)):
                 raise ValueError(f"{name} has the wrong shape {tuple(t.shape)}")
         st = lib().gls_block(self.handle, mb, _ptr(XR), self.n,
-                             _ptr(b), self.p, _ptr(sigma2), _ptr(v), _ptr(status), _stream(stream))
+                             _ptr(b), self.p, _ptr(sigma2), _ptr(v), _ptr(status), self._use(stream))
         _check(st)
 
     def _dosage_block_into(self, entry, rowbytes, G, b, sigma2, v, status, stream):
@@ -225,7 +237,7 @@ class GLSContext:
             if t.shape[0] != mb or (name == "b" and tuple(t.shape) != (mb, self.p)):
                 raise ValueError(f"{name} has the wrong shape {tuple(t.shape)}")
         _check(entry(self.handle, mb, _ptr(G), rowbytes, _ptr(b), self.p, _ptr(sigma2), _ptr(v),
-                     _ptr(status), _stream(stream)))
+                     _ptr(status), self._use(stream)))
 
     def _outputs(self, mb, dev):
         return (torch.empty((mb, self.p), dtype=torch.float64, device=dev),
@@ -281,8 +293,8 @@ class GLSContext:
         cs = compute_stream or torch.cuda.current_stream()
         xs = copy_stream or torch.cuda.Stream()
         st = lib().gls_stream_file(self.handle, path.encode(), offset, elem, m, col0, _ptr(host_ws), host_ws.numel(),
-                                   _ptr(b), _ptr(s2), _ptr(v), _ptr(status), ctypes.c_void_p(cs.cuda_stream),
-                                   ctypes.c_void_p(xs.cuda_stream), ctypes.byref(stats))
+                                   _ptr(b), _ptr(s2), _ptr(v), _ptr(status), self._use(cs), self._use(xs),
+                                   ctypes.byref(stats))
         _check(st)
         return (b, s2, v, status), stats
 
@@ -320,8 +332,7 @@ class GLSContext:
         cs = compute_stream or torch.cuda.current_stream()
         xs = copy_stream or torch.cuda.Stream()
         st = entry(self.handle, m, col0, _ptr(XR_host), rowlen, _ptr(b), _ptr(s2), _ptr(v),
-                   _ptr(status), ctypes.c_void_p(cs.cuda_stream), ctypes.c_void_p(xs.cuda_stream),
-                   ctypes.byref(stats))
+                   _ptr(status), self._use(cs), self._use(xs), ctypes.byref(stats))
         _check(st)
         return (b, s2, v, status), stats
 

@@ -34,6 +34,7 @@ STREAM_XL = 2
 STREAM_XR = 3
 STREAM_Y = 4
 STREAM_CAUSAL = 5
+STREAM_JITTER = 6
 SNP_CHUNK = 1024
 BASE_SEED = 4332
 
@@ -155,6 +156,28 @@ def genotypes(n: int, j0: int, j1: int, seed: int, out: np.ndarray | None = None
         return g.astype(np.float64)
     out[...] = g
     return out
+
+
+def imputed_dosages(n: int, j0: int, j1: int, seed: int, kind: str = "jitter") -> np.ndarray:
+    """Real-valued SNP columns [j0, j1), shape (j1-j0, n): the dosages of
+    ``genotypes`` made non-integer, as imputed or normalised genotype data are.
+
+    kind "jitter": dosage + U(-0.5, 0.5) (imputation-like expected dosages);
+    kind "standardized": each SNP column centred and scaled to unit population
+    s.d. (a constant column is left at zero)."""
+    g = genotypes(n, j0, j1, seed)
+    if kind == "jitter":
+        for k in range(j0 // SNP_CHUNK, (j1 - 1) // SNP_CHUNK + 1 if j1 > j0 else 0):
+            rng = np.random.default_rng([seed, STREAM_JITTER, k])
+            u = rng.uniform(-0.5, 0.5, size=(SNP_CHUNK, n))
+            lo, hi = max(j0, k * SNP_CHUNK), min(j1, (k + 1) * SNP_CHUNK)
+            g[lo - j0:hi - j0] += u[lo - k * SNP_CHUNK:hi - k * SNP_CHUNK]
+        return g
+    if kind == "standardized":
+        mu = g.mean(axis=1, keepdims=True)
+        sd = g.std(axis=1, keepdims=True)
+        return np.where(sd > 0, (g - mu) / np.where(sd > 0, sd, 1.0), 0.0)
+    raise ValueError(kind)
 
 
 def pack_dosages_2bit(g: np.ndarray) -> np.ndarray:

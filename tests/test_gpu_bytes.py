@@ -12,6 +12,7 @@ import torch
 from oracle import gls_oracle as O
 from paper_1302_4332_amd import synth
 from paper_1302_4332_amd.gls import GLSContext
+from parity_util import as_numpy, compare
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -80,12 +81,14 @@ def test_int8_emulation_block_independent_and_streamed():
     (bs, s2, v, st), stats = ctx.stream(torch.tensor(G).pin_memory())
     assert stats.h2d_bytes == 600 * 700
     assert np.array_equal(bs.numpy(), a["b"]) and np.array_equal(st.numpy(), a["status"])
+    compare(as_numpy((bs, s2, v, st)), O.gls_sequence(Phi, 0.4, XL, y, G.astype(np.float64)), 1e-10)
 
 
 def test_bytes_stream_fp64_equals_double_stream():
     Phi, XL, y, G = _inputs(330, 4, 500, 12, "sex_age")
     ctx = GLSContext(_t(Phi), 0.4, _t(XL), _t(y), block_cols=128)
-    (b1, *_), s1 = ctx.stream(torch.tensor(G).pin_memory())
+    out1, s1 = ctx.stream(torch.tensor(G).pin_memory())
     (b2, *_), s2 = ctx.stream(torch.tensor(G.astype(np.float64)).pin_memory())
     assert s1.h2d_bytes * 8 == s2.h2d_bytes
-    assert np.array_equal(b1.numpy(), b2.numpy(), equal_nan=True)
+    assert np.array_equal(out1[0].numpy(), b2.numpy(), equal_nan=True)
+    compare(as_numpy(out1), O.gls_sequence(Phi, 0.4, XL, y, G.astype(np.float64)), 1e-10)

@@ -5,12 +5,12 @@ sum_i t_i^2 from the hand-written adjoint.
 
 The SNPs are the study's first block of 16,384 and a ragged block of 1,152
 (2,000,000 mod 16,384), in the same block configuration as the full study.
-At this size the FP64 autograd reference is out of reach, so the checks are
-the ones that hold at any size:
+At this size the FP64 autograd reference is out of reach, so the checks are:
 - the refined forward against the oracle on sampled SNPs (bar 1e-8);
-- the adjoint's d loss / d h^2 against central differences of the GPU loss
-  itself (step 1e-6, both sides full re-solves including the Cholesky), with the
-  gradient tolerance |FD - g| <= 1e-5 max(|FD|, |g|);
+- the adjoint's d loss / d h^2 against central differences of the CPU
+  oracle's loss on the same 17,536 SNPs (step 1e-6, full re-solves including
+  the Cholesky of M at h^2 +- 1e-6), and against central differences of the GPU
+  loss itself, both with the gradient tolerance |FD - g| <= 1e-5 max(|FD|, |g|);
 - peak device memory below half of the device's memory.
 """
 import numpy as np
@@ -38,6 +38,15 @@ def _loss(Phi, XL, y, X, h2, bc):
     return float(t2_loss(b, s2, v)), b
 
 
+def _oracle_loss(st, h2, Xh):
+    """Sum of t^2 over the SNPs of Xh (one per row) from the CPU oracle."""
+    ost = O.Study(st.Phi, h2, st.XL, st.y)
+    r = ost.block(Xh.T)
+    assert (r["status"] == 0).all()
+    return O.loss_t2(r["b"], r["sigma2"], r["v"])
+
+
+@pytest.mark.timeout(1500)
 def test_n20k_p8_refined_fp32_with_h2_gradient():
     w = synth.WORKLOADS["c4_n20k_p8"]
     st = synth.make_study(w)
@@ -63,6 +72,14 @@ def test_n20k_p8_refined_fp32_with_h2_gradient():
     fd = (lp - lm) / (2 * eps)
     print(f"loss {float(loss.detach()):.6e}  d/dh2 adjoint {g:.9e}  central difference {fd:.9e}", flush=True)
     assert abs(fd - g) <= 1e-5 * max(abs(fd), abs(g))
+
+    # the same derivative from the CPU oracle: central differences of its loss
+    lpo = _oracle_loss(st, w.h2 + eps, Xh)
+    print("oracle loss at h2 + 1e-6 done", flush=True)
+    lmo = _oracle_loss(st, w.h2 - eps, Xh)
+    fdo = (lpo - lmo) / (2 * eps)
+    print(f"oracle loss {0.5 * (lpo + lmo):.6e}  oracle central difference {fdo:.9e}", flush=True)
+    assert abs(fdo - g) <= 1e-5 * max(abs(fdo), abs(g))
 
     # refined forward against the oracle on sampled SNPs of both blocks
     rng = np.random.default_rng(7)

@@ -2,8 +2,9 @@
 expanded on the device.  The expansion is exact, so results must be bitwise
 those of the byte entry points on the same dosages, for FP64, refined and
 int8-slice handles.  Pad bits of a column's last byte are ignored and the
-column stride may exceed a column; the oracle bar (max relative error of b
-<= 1e-10) is checked directly on one case."""
+column stride may exceed a column.  The oracle bar (max relative error of b
+<= 1e-10, sigma2 and v relative 1e-10, status equal) is checked directly on a
+block, on the in-memory and file streams and on a resumed stream."""
 import ctypes
 
 import numpy as np
@@ -13,6 +14,7 @@ import torch
 from oracle import gls_oracle as O
 from paper_1302_4332_amd import synth
 from paper_1302_4332_amd.gls import GLSContext, GLSError, lib
+from parity_util import as_numpy, compare, slice_out
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -111,6 +113,7 @@ def test_stream_u2_equals_bytes_stream(precision):
     assert st2.h2d_bytes == ((n + 3) // 4) * m and st8.h2d_bytes == n * m
     for x, z in ((b8, b2), (s8, s2), (v8, v2), (t8, t2)):
         assert np.array_equal(x.numpy(), z.numpy(), equal_nan=True)
+    compare(as_numpy((b2, s2, v2, t2)), O.gls_sequence(Phi, 0.4, XL, y, G.astype(np.float64)), 1e-10)
 
 
 @pytest.mark.parametrize("serial", [False, True])
@@ -123,9 +126,11 @@ def test_file_stream_u2_equals_bytes(tmp_path, serial):
         f.write(synth.pack_dosages_2bit(G).tobytes())
     ctx = GLSContext(_t(Phi), 0.4, _t(XL), _t(y), block_cols=96, serial_stream=serial)
     (ref_b, _, _, ref_st), _ = ctx.stream(torch.tensor(G).pin_memory())
-    (b, _, _, st), stats = ctx.stream_file(f2, m, "u2", offset=7)
+    res, stats = ctx.stream_file(f2, m, "u2", offset=7)
+    b, st = res[0], res[3]
     assert stats.blocks == 11 and stats.file_bytes == ((n + 3) // 4) * m
     assert np.array_equal(b.numpy(), ref_b.numpy()) and np.array_equal(st.numpy(), ref_st.numpy())
+    compare(as_numpy(res), O.gls_sequence(Phi, 0.4, XL, y, G.astype(np.float64)), 1e-10)
     with pytest.raises(GLSError) as e:
         ctx.stream_file(f2, m + 60, "u2", offset=7)   # file shorter than m columns
     assert e.value.status == -5
@@ -165,6 +170,9 @@ def test_u2_no_covariates_and_stream_resume():
     f = torch.float64
     out = (torch.full((m, 1), -7.0, dtype=f).pin_memory(), torch.zeros(m, dtype=f).pin_memory(),
            torch.zeros(m, dtype=f).pin_memory(), torch.zeros(m, dtype=torch.int32).pin_memory())
-    (part, *_), stats = ctx.stream(Ph, col0=333, out=out, packed=True)
+    res, stats = ctx.stream(Ph, col0=333, out=out, packed=True)
+    part = res[0]
     assert stats.h2d_bytes == ((n + 3) // 4) * (m - 333)
     assert (part.numpy()[:333] == -7.0).all() and np.array_equal(part.numpy()[333:], full.numpy()[333:])
+    r = O.gls_sequence(Phi, 0.5, np.zeros((n, 0)), y, G[333:].astype(np.float64))
+    compare(slice_out(as_numpy(res), 333), r, 1e-10)

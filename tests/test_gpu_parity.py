@@ -1,7 +1,9 @@
 """GPU parity of the FP64 path against the CPU oracle, through the C-ABI.
 
 Tolerances (plain FP64): per SNP, ||b_i - b_i,oracle||_inf / ||b_i,oracle||_inf
-<= 1e-10, and relative 1e-10 on sigma2_i and v_i; status bit-exact.
+<= 1e-10, and relative 1e-10 on sigma2_i and v_i; status bit-exact.  Streamed
+outputs (overlapped, serial, resumed, with the opening ramp) are held to the
+same bar against the oracle, and are also bitwise those of the block path.
 """
 import numpy as np
 import pytest
@@ -10,6 +12,7 @@ import torch
 from oracle import gls_oracle as O
 from paper_1302_4332_amd import synth
 from paper_1302_4332_amd.gls import GLSContext, GLSError
+from parity_util import as_numpy, compare, slice_out
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -150,6 +153,10 @@ def test_stream_matches_block_and_resumes():
     assert (b2.numpy()[:700] == -7.0).all()
     assert np.array_equal(b2.numpy()[700:], ref["b"][700:])
     assert np.array_equal(st2.numpy()[700:], ref["status"][700:])
+    # both streamed outputs against the oracle
+    r = O.gls_sequence(Phi, h2, XL, y, XR)
+    compare(as_numpy((b, s2, v, st)), r, TOL_B)
+    compare(slice_out(as_numpy((b2, s22, v2, st2)), 700), slice_out(r, 700), TOL_B)
 
 
 def test_serial_stream_equals_overlapped():
@@ -159,9 +166,11 @@ def test_serial_stream_equals_overlapped():
     a = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=128)
     b = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=128, serial_stream=True)
     (ra, _, _, sa), _ = a.stream(host)
-    (rb, _, _, sb), stats = b.stream(host)
+    outb, stats = b.stream(host)
+    rb, sb = outb[0], outb[3]
     assert stats.blocks == 6 and stats.h2d_bytes == 8 * 330 * 700
     assert np.array_equal(ra.numpy(), rb.numpy()) and np.array_equal(sa.numpy(), sb.numpy())
+    compare(as_numpy(outb), O.gls_sequence(Phi, h2, XL, y, XR), TOL_B)
 
 
 def _ramp_blocks(m, col0, bc):
@@ -187,9 +196,13 @@ def test_stream_ramp_bitwise():
     assert stats.blocks == _ramp_blocks(9000, 0, bc) == 10
     assert np.array_equal(b.numpy(), ref["b"]) and np.array_equal(s2.numpy(), ref["sigma2"])
     assert np.array_equal(v.numpy(), ref["v"]) and np.array_equal(st.numpy(), ref["status"])
-    (b2, _, _, st2), stats2 = ctx.stream(host, col0=300)
+    out2, stats2 = ctx.stream(host, col0=300)
+    b2, st2 = out2[0], out2[3]
     assert stats2.blocks == _ramp_blocks(9000, 300, bc)
     assert np.array_equal(b2.numpy()[300:], ref["b"][300:]) and np.array_equal(st2.numpy()[300:], ref["status"][300:])
+    r = O.gls_sequence(Phi, h2, XL, y, XR)
+    compare(as_numpy((b, s2, v, st)), r, TOL_B)
+    compare(slice_out(as_numpy(out2), 300), slice_out(r, 300), TOL_B)
 
 
 def test_empty_inputs():

@@ -54,3 +54,16 @@ def test_pack_dosages_2bit_round_trip(n):
     assert P.shape == (9, (n + 3) // 4)
     back = np.stack([(P[:, k // 4] >> (2 * (k % 4))) & 3 for k in range(n)], axis=1)
     assert np.array_equal(back, g)
+
+
+def test_imputed_dosages():
+    """Non-integer SNP values: jitter within half a dosage of the genotype and
+    independent of the block split; standardized columns have mean 0 and s.d. 1."""
+    g = synth.genotypes(97, 1000, 1100, 5)
+    j = synth.imputed_dosages(97, 1000, 1100, 5)
+    assert j.shape == g.shape and np.all(np.abs(j - g) <= 0.5)
+    assert np.mean(j != np.round(j)) > 0.99
+    parts = np.concatenate([synth.imputed_dosages(97, 1000, 1030, 5), synth.imputed_dosages(97, 1030, 1100, 5)])
+    assert np.array_equal(parts, j)
+    s = synth.imputed_dosages(97, 0, 40, 5, "standardized")
+    assert np.allclose(s.mean(axis=1), 0.0, atol=1e-12) and np.allclose(s.std(axis=1), 1.0)
