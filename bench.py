@@ -16,6 +16,7 @@ included, is reported as hbm_resident.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -34,7 +35,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32_ir": 157.3, "fp16_ir": 2500.0, "bf16_ir": 250
 # two rocprofv3 --pmc runs (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, factors
 # from a 1 GiB device copy; summary in profiles/).  Valid only while the
 # kernel source is the one those counters were taken on.
-TRAFFIC_RECORD = {"kernel_sha1": "32a87d13753b7a1e", "n": 10000, "block_cols": 8192, "bytes_per_launch": 29.54e9}
+TRAFFIC_RECORD = {"kernel_sha1": "0e869db303c59d11", "n": 10000, "block_cols": 8192, "bytes_per_launch": 28.94e9}
 
 
 def kernel_hash() -> str:
@@ -404,6 +405,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1_n10k_m100k")
     ap.add_argument("--m", type=int, default=None, help="override the SNP count")
+    ap.add_argument("--n", type=int, default=None, help="override the sample count (e.g. 10007: n not a multiple "
+                    "of the product's k step)")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--sweeps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -434,6 +437,8 @@ def main():
     from paper_1302_4332_amd.gls import GLSContext, make_opts, workspace_bytes
 
     w = synth.WORKLOADS[args.workload]
+    if args.n:
+        w = dataclasses.replace(w, n=args.n, name=f"{w.name}_n{args.n}")
     m = args.m or w.m
     n, p, bc, h2 = w.n, w.p, w.block_cols, w.h2
     dev = torch.device("cuda:0")

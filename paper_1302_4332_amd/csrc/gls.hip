@@ -132,9 +132,8 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
     pl->off_ubp = take((size_t)N * pl->bcp);
     pl->off_sl = take((size_t)OZ_SLICES * N * N);
     pl->off_ex = take(sizeof(int) * N);
-  } else {
-    pl->off_x64 = take(sizeof(double) * N * bc);
   }
+  pl->off_x64 = take(sizeof(double) * N * bc);
   if (pl->lp_bytes) {
     pl->off_Llp = take((size_t)pl->lp_bytes * N * N);
     pl->off_Blp = take((size_t)pl->lp_bytes * N * pl->bcp);
@@ -340,7 +339,7 @@ static void chol_inv_rec(Ctx* c, int a, int b, int depth, SetupSide* side, hipSt
       gemm(false, true, big_product(w2, w2), g, s);
     }
   }
-  const bool on_side = big_product(w2, w1) && depth < 16;
+  const bool on_side = big_product(w2, w1) && depth < 16 && side->st != nullptr;
   if (on_side) {   // T = L21 L11^-1 on the side stream, into this depth's region
     T = side->base + c->plan.side_at[depth];
     side->check(hipEventRecord(side->fork, s));
@@ -391,9 +390,12 @@ static void tri_apply(Ctx* c, const double* V, double* part, double* W, hipStrea
   }
 }
 
-// X~ (N x mb, ld N) = L^-1 X   for an n x mb block X (ld ldx); rows >= n of X read as 0.
-void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, double* Xt, hipStream_t s) {
-  GemmArgs g = gemm_args(c->Linv, c->N, X, ldx, Xt, c->N, (int)c->N, mb, (int)c->n, 1.0);
+// X~ (rows x mb, ld N) = L^-1 X   for an n x mb block X (ld ldx) summed over
+// its first K rows: K = n, or n rounded up to 16 when X's rows n..K-1 are
+// zero.  rows = N, or n rounded up to the product's 128-row tiles when only
+// the sample rows (and the zero rows up to that tile edge) are read later.
+void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, int K, int rows, double* Xt, hipStream_t s) {
+  GemmArgs g = gemm_args(c->Linv, c->N, X, ldx, Xt, c->N, rows, mb, K, 1.0);
   g.a_tri = TRI_LOWER;
   g.a_diag = 0;
   g.map_desc = 1;
@@ -426,51 +428,36 @@ void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, 
 // ---------------------------------------------------------------------------
 // C-ABI
 
-extern "C" {
+namespace gls {
 
-const char* gls_status_string(gls_status s) {
-  switch (s) {
-    case GLS_OK: return "ok";
-    case GLS_ERR_ARG: return "invalid argument";
-    case GLS_ERR_NOT_SPD: return "M is not positive definite";
-    case GLS_ERR_HIP: return "HIP runtime error";
-    case GLS_ERR_WORKSPACE: return "workspace too small or misaligned";
-    case GLS_ERR_STATE: return "call not valid in this state";
-    case GLS_ERR_RANK: return "covariates are rank deficient";
+// Argument checks of gls_setup; fills the plan.
+static gls_status setup_args(const char* fn, int64_t n, int32_t p, const double* Phi, int64_t ld_phi, double h2,
+                             const double* XL, int64_t ld_xl, const double* y, const gls_opts* opts, Plan* pl) {
+  if (!plan_workspace(n, p, opts, pl)) {
+    set_err("%s: invalid n/p/opts (need 1 <= p <= 20, n > p)", fn);
+    return GLS_ERR_ARG;
   }
-  return "unknown status";
+  const char* bad = nullptr;
+  if (!Phi || ld_phi < n) bad = "Phi is NULL or ld_phi < n";
+  else if (p > 1 && (!XL || ld_xl < n)) bad = "XL is NULL or ld_xl < n";
+  else if (!y) bad = "y is NULL";
+  else if (!(h2 >= 0.0 && h2 <= 1.0)) bad = "h2 must lie in [0, 1]";
+  if (bad) {
+    set_err("%s: %s", fn, bad);
+    return GLS_ERR_ARG;
+  }
+  return GLS_OK;
 }
 
-const char* gls_last_error(void) { return g_err; }
-
-size_t gls_workspace_bytes(int64_t n, int32_t p, const gls_opts* opts) {
-  Plan pl;
-  if (!plan_workspace(n, p, opts, &pl)) return 0;
-  return pl.total;
-}
-
-gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, int64_t ld_phi, double h2,
-                     const double* XL, int64_t ld_xl, const double* y, void* workspace, size_t ws_bytes,
-                     const gls_opts* opts, void* stream, int64_t* info) {
-  if (info) *info = 0;
-  if (!out) return arg_fail("gls_setup: out is NULL");
-  *out = nullptr;
-  Plan pl;
-  if (!plan_workspace(n, p, opts, &pl)) return arg_fail("gls_setup: invalid n/p/opts (need 1 <= p <= 20, n > p)");
-  if (!Phi || ld_phi < n) return arg_fail("gls_setup: Phi is NULL or ld_phi < n");
-  if (p > 1 && (!XL || ld_xl < n)) return arg_fail("gls_setup: XL is NULL or ld_xl < n");
-  if (!y) return arg_fail("gls_setup: y is NULL");
-  if (!(h2 >= 0.0 && h2 <= 1.0)) return arg_fail("gls_setup: h2 must lie in [0, 1]");
-  if (!workspace || ((uintptr_t)workspace & 255)) {
-    set_err("gls_setup: workspace is NULL or not 256-byte aligned");
-    return GLS_ERR_WORKSPACE;
-  }
-  if (ws_bytes < pl.total) {
-    set_err("gls_setup: workspace has %zu bytes, needs %zu", ws_bytes, pl.total);
-    return GLS_ERR_WORKSPACE;
-  }
-  Ctx* c = new (std::nothrow) Ctx();
-  if (!c) return arg_fail("gls_setup: out of host memory");
+// The study setup (Sec. 2.1, Listing 1 before the SNP loop) into a fresh
+// handle c whose regions lie in the workspace ws (plan pl).  With side_stream
+// the products T = L21 L11^-1 of big recursion nodes overlap on a side stream;
+// without it every kernel runs on s (the same kernels in the same order per
+// output, so the same results).  Synchronizes s: on return nothing enqueued
+// here still runs.
+static gls_status setup_into(Ctx* c, const Plan& pl, int64_t n, int32_t p, const double* Phi, int64_t ld_phi,
+                             double h2, const double* XL, int64_t ld_xl, const double* y, char* ws,
+                             const gls_opts* opts, bool side_stream, hipStream_t s, int64_t* info) {
   c->plan = pl;
   c->opts = *opts;
   c->n = n;
@@ -478,7 +465,6 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   c->N = pl.N;
   c->bc = pl.bc;
   c->h2 = h2;
-  char* ws = static_cast<char*>(workspace);
   c->info = reinterpret_cast<int*>(ws + pl.off_info);
   c->small = reinterpret_cast<double*>(ws + pl.off_small);
   c->gram = reinterpret_cast<double*>(ws + pl.off_gram);
@@ -492,14 +478,12 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   c->os2 = reinterpret_cast<double*>(ws + pl.off_os2);
   c->ov = reinterpret_cast<double*>(ws + pl.off_ov);
   c->ost = reinterpret_cast<int*>(ws + pl.off_ost);
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t N = c->N;
 
   hipError_t e;
   int hinfo[2] = {0, 0};
   auto fail = [&](gls_status st) {   // nothing enqueued here may still run on the caller's workspace
     (void)hipStreamSynchronize(s);
-    delete c;
     return st;
   };
   // info[0]: failing pivot of M, info[1]: failing pivot of S_TL
@@ -508,7 +492,7 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Linv, N * N, 0.0);
   {
     SetupSide side;
-    if ((e = side.init(reinterpret_cast<double*>(ws + pl.off_side))) != hipSuccess)
+    if (side_stream && (e = side.init(reinterpret_cast<double*>(ws + pl.off_side))) != hipSuccess)
       return fail(hip_fail(e, "gls_setup: side stream"));
     chol_inv_rec(c, 0, (int)(N / NB_LEAF), 0, &side, s);
     // every side product is joined into s by its node's last product
@@ -523,9 +507,8 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
     hipLaunchKernelGGL(row_exponent_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, c->Linv, (int)N, c->ex);
     hipLaunchKernelGGL(slice_factor_kernel, dim3((unsigned)(N / 64), (unsigned)(N / 64)), dim3(256), 0, s, c->Linv,
                        (int)N, (const int*)c->ex, c->sl);
-  } else {
-    c->x64 = reinterpret_cast<double*>(ws + pl.off_x64);
   }
+  c->x64 = reinterpret_cast<double*>(ws + pl.off_x64);
   if (pl.lp_bytes) {
     c->Llp = ws + pl.off_Llp;
     c->Blp = ws + pl.off_Blp;
@@ -572,6 +555,60 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
     set_err("gls_setup: S_TL = X~_L^T X~_L is not positive definite at covariate %d", hinfo[1]);
     return fail(GLS_ERR_RANK);
   }
+  return GLS_OK;
+}
+
+}  // namespace gls
+
+extern "C" {
+
+const char* gls_status_string(gls_status s) {
+  switch (s) {
+    case GLS_OK: return "ok";
+    case GLS_ERR_ARG: return "invalid argument";
+    case GLS_ERR_NOT_SPD: return "M is not positive definite";
+    case GLS_ERR_HIP: return "HIP runtime error";
+    case GLS_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case GLS_ERR_STATE: return "call not valid in this state";
+    case GLS_ERR_RANK: return "covariates are rank deficient";
+  }
+  return "unknown status";
+}
+
+const char* gls_last_error(void) { return g_err; }
+
+size_t gls_workspace_bytes(int64_t n, int32_t p, const gls_opts* opts) {
+  Plan pl;
+  if (!plan_workspace(n, p, opts, &pl)) return 0;
+  return pl.total;
+}
+
+gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, int64_t ld_phi, double h2,
+                     const double* XL, int64_t ld_xl, const double* y, void* workspace, size_t ws_bytes,
+                     const gls_opts* opts, void* stream, int64_t* info) {
+  if (info) *info = 0;
+  if (!out) return arg_fail("gls_setup: out is NULL");
+  *out = nullptr;
+  Plan pl;
+  gls_status st = setup_args("gls_setup", n, p, Phi, ld_phi, h2, XL, ld_xl, y, opts, &pl);
+  if (st != GLS_OK) return st;
+  if (!workspace || ((uintptr_t)workspace & 255)) {
+    set_err("gls_setup: workspace is NULL or not 256-byte aligned");
+    return GLS_ERR_WORKSPACE;
+  }
+  if (ws_bytes < pl.total) {
+    set_err("gls_setup: workspace has %zu bytes, needs %zu", ws_bytes, pl.total);
+    return GLS_ERR_WORKSPACE;
+  }
+  Ctx* c = new (std::nothrow) Ctx();
+  if (!c) return arg_fail("gls_setup: out of host memory");
+  st = setup_into(c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, static_cast<char*>(workspace), opts, true,
+                  static_cast<hipStream_t>(stream), info);
+  if (st != GLS_OK) {
+    delete c;
+    return st;
+  }
+  hipError_t e;
   for (int i = 0; i < 2; ++i) {
     if ((e = hipEventCreateWithFlags(&c->ev_copy[i], hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->ev_comp[i], hipEventDisableTiming)) != hipSuccess) {
@@ -796,8 +833,31 @@ static void lp_solve(Ctx* c, const double* src, int64_t lds, int mb, double beta
 }
 
 // R (rows < n) = X - L Xt in FP64 (the refinement residual).
+// n rounded up to the product kernel's k step; rows n..N-1 of L, L^-1 and of
+// every whitened block are zero off the identity padding, so sums may run to it.
+static int k16(const Ctx* c) { return (int)((c->n + DB_BK - 1) / DB_BK * DB_BK); }
+
+// The FP64 block operand of the product with L^-1: X itself when its layout
+// feeds the direct-load kernel (n a multiple of 16, 16-byte aligned, even
+// ld), else a copy in c->x64 (ld N) whose rows n..K-1 are zero.  Blocks
+// already in c->x64 (widened bytes) carry zero rows up to N.  Sets *K, the
+// rows the product sums over.
+static const double* fp64_operand(Ctx* c, const double* X, int64_t* ldx, int mb, int* K, hipStream_t s) {
+  if (X == c->x64) {
+    *K = k16(c);
+    return X;
+  }
+  *K = (int)c->n;
+  if (dma_b_operand_ok(X, *ldx, c->n)) return X;
+  *K = k16(c);
+  hipLaunchKernelGGL(pad_copy_kernel, dim3(grid_for((int64_t)*K * mb)), dim3(256), 0, s, c->x64, c->N, X, *ldx,
+                     (int)c->n, *K, mb);
+  *ldx = c->N;
+  return c->x64;
+}
+
 static void residual_fp64(Ctx* c, const double* X, int64_t ldx, int mb, hipStream_t s) {
-  GemmArgs g = gemm_args(c->L, c->N, c->Xt, c->N, c->R, c->N, (int)c->n, mb, (int)c->n, -1.0);
+  GemmArgs g = gemm_args(c->L, c->N, c->Xt, c->N, c->R, c->N, (int)c->n, mb, k16(c), -1.0);
   g.Cin = X;
   g.ldcin = ldx;
   g.beta = 1.0;
@@ -824,7 +884,12 @@ gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double
     }
   } else {
     PhaseTimer t(c, PH_WHITEN, s);
-    whiten_fp64(c, XR, ld_xr, mb, c->Xt, s);
+    int K = 0;
+    const double* X = fp64_operand(c, XR, &ld_xr, mb, &K, s);
+    // the per-SNP sums read rows < n, the residual rows < n rounded up to 16:
+    // row tiles wholly past n are not computed
+    const int rows = (int)((c->n + DB_BM - 1) / DB_BM * DB_BM);
+    whiten_fp64(c, X, ld_xr, mb, K, rows, c->Xt, s);
   }
   {
     PhaseTimer t(c, PH_SNP, s);
@@ -940,7 +1005,9 @@ static void recompute_whitened(Ctx* c, int mb, const double* XR, int64_t ld_xr, 
       lp_solve(c, c->R, c->N, mb, 1.0, s);
     }
   } else {
-    whiten_fp64(c, XR, ld_xr, mb, c->Xt, s);
+    int K = 0;
+    const double* X = fp64_operand(c, XR, &ld_xr, mb, &K, s);
+    whiten_fp64(c, X, ld_xr, mb, K, (int)c->N, c->Xt, s);
   }
 }
 

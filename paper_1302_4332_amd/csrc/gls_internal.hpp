@@ -68,7 +68,7 @@ struct gls_ctx {
   // byte input
   uint8_t* ub[2] = {nullptr, nullptr};  // streaming staging, n x block_cols bytes
   uint8_t* ubp = nullptr;   // N x bcp packed bytes (GLS_INT8_EMU operand)
-  double* x64 = nullptr;    // N x block_cols bytes widened to FP64 (other precisions)
+  double* x64 = nullptr;    // N x block_cols FP64: bytes widened, or a block copied with zero rows past n
   int8_t* sl = nullptr;     // OZ_SLICES x N x N int8 slices of L^-1 (GLS_INT8_EMU)
   int* ex = nullptr;        // N row exponents of L^-1 (GLS_INT8_EMU)
   // adjoint state (GLS_KEEP_FOR_GRAD)
@@ -124,7 +124,7 @@ void set_last_error_str(const char* what);
 int64_t padded_n(int64_t n);
 bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl);
 
-void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, double* Xt, hipStream_t s);
+void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, int K, int rows, double* Xt, hipStream_t s);
 void prepare_low_precision(Ctx* c, hipStream_t s);
 void reset_adjoint(Ctx* c, hipStream_t s);
 void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,

@@ -29,6 +29,21 @@ __device__ __forceinline__ void lds_load16(const void* src, uint32_t lds) {
       : "memory");
 }
 
+// The same load addressed as a wave-uniform 64-bit base (scalar registers)
+// plus a 32-bit byte offset per lane, which saves two address VGPRs per load
+// stream against lds_load16.
+__device__ __forceinline__ void lds_load16_sv(const void* sbase, uint32_t voff, uint32_t lds) {
+  uint32_t keep;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %3\n\t"
+      "global_load_lds_dwordx4 %1, %2\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(keep)
+      : "v"(voff), "s"(sbase), "s"(lds)
+      : "memory");
+}
+
 // Wait until at most N of this wave's vector-memory loads are in flight.
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {

@@ -46,6 +46,19 @@ __global__ void copy2d_kernel(double* __restrict__ dst, int64_t ld_dst,
   }
 }
 
+// dst[k + j ld_dst] = src[k + j ld_src] for k < n, 0 for n <= k < rows, over
+// cols columns: a block copied into a buffer whose rows past n are zero.
+__global__ void pad_copy_kernel(double* __restrict__ dst, int64_t ld_dst, const double* __restrict__ src,
+                                int64_t ld_src, int n, int rows, int cols) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)rows * cols;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % rows);
+    const int j = (int)(idx / rows);
+    dst[(int64_t)i + (int64_t)j * ld_dst] = (i < n) ? src[(int64_t)i + (int64_t)j * ld_src] : 0.0;
+  }
+}
+
 // dst (cols x rows, ld_dst) <- src^T for src (rows x cols, ld_src), through
 // 32 x 32 LDS tiles so that both the reads and the writes are column runs.
 __global__ __launch_bounds__(256) void transpose_kernel(double* __restrict__ dst, int64_t ld_dst,

@@ -75,9 +75,11 @@ __device__ __forceinline__ void snp_solve(const double* __restrict__ small, cons
   *status = 0;
 }
 
-// One wave per SNP_PER_WAVE SNP columns of Xt (N x mb, ld ldx).  W = [X~_L | y~]
-// (N x P, ld N).  Lane-strided row sums, then a fixed butterfly reduction:
-// every SNP's arithmetic depends only on its own column.
+// One wave per SNP_PER_WAVE SNP columns of Xt (rows 0..n-1 read, ld ldx).
+// W = [X~_L | y~] (N x P, ld N).  Lane-strided row sums over the n sample
+// rows (the padding rows of W are zero, those of Xt need not be written),
+// then a fixed butterfly reduction: every SNP's arithmetic depends only on
+// its own column.
 template <int P>
 __global__ __launch_bounds__(64 * SNP_WAVES)
 void snp_reduce_solve_kernel(const double* __restrict__ Xt, int64_t ldx, int N, int mb,
@@ -99,7 +101,7 @@ void snp_reduce_solve_kernel(const double* __restrict__ Xt, int64_t ldx, int N, 
     int c = c0 + s < mb ? c0 + s : c0;   // clamp: a repeated column, result discarded
     xs[s] = Xt + (int64_t)c * ldx;
   }
-  for (int r = lane; r < N; r += 64) {
+  for (int r = lane; r < n; r += 64) {
     double w[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) w[j] = W[r + (int64_t)j * N];

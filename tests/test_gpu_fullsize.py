@@ -10,7 +10,11 @@ sampled SNPs that the CPU oracle solves one by one.
   FP16 two and three; BF16 three and four: the fewest sweeps that meet the bar
   and the counts that reach the FP64 level);
 - n = 20,000, p = 8 (Gaussian covariates), blocks of 16,384: the first block and
-  a ragged block of 1,152 (2,000,000 mod 16,384).
+  a ragged block of 1,152 (2,000,000 mod 16,384);
+- n = 10,007 (not a multiple of the product's 16-deep k step, odd leading
+  dimension), otherwise the n = 10,000 study: the first block and the last
+  (1,696 SNPs), plain FP64 (the block is first copied into a zero-padded
+  buffer so that the direct-load product applies) and refined FP32.
 
 Bar: per SNP ||b - b_oracle||_inf / ||b_oracle||_inf <= 1e-10 for the plain
 FP64 and int8-slice paths, 1e-8 for the refined forms; sigma2 and v relative
@@ -43,9 +47,9 @@ def _check(g, r, tol):
     return float(err.max())
 
 
-def _study_blocks(name, tail):
+def _study_blocks(name, tail, n=None):
     w = synth.WORKLOADS[name]
-    st = synth.make_study(w)
+    st = synth.make_study(w, n=n) if n else synth.make_study(w)
     bc = w.block_cols
     first = (0, bc)
     last = (w.m - tail, w.m)
@@ -58,10 +62,10 @@ def _sample(j0, j1, k, seed):
     return np.unique(np.r_[j0, j1 - 1, rng.integers(j0, j1, size=k)])
 
 
-def _run(name, tail, forms, k=48):
+def _run(name, tail, forms, k=48, n=None):
     """forms: (precision, refinement sweeps, input) with input "f64", "u8" or "u2"."""
-    w, st, bc, blocks = _study_blocks(name, tail)
-    print(f"{name}: n={w.n} p={w.p} blocks {blocks}", flush=True)
+    w, st, bc, blocks = _study_blocks(name, tail, n)
+    print(f"{name}: n={st.Phi.shape[0]} p={w.p} blocks {blocks}", flush=True)
     ost = O.Study(st.Phi, w.h2, st.XL, st.y)
     Phi, XL, y = _t(st.Phi), _t(st.XL), _t(st.y)
     errs = {}
@@ -98,3 +102,7 @@ def test_fullsize_n10k_m1M_mixed():
 
 def test_fullsize_n20k_p8_fp64():
     _run("c4_n20k_p8", 2000000 % 16384, (("fp64", 0, "f64"),))
+
+
+def test_fullsize_n10007_fp64_and_refined():
+    _run("c1_n10k_m100k", 100000 % 8192, (("fp64", 0, "f64"), ("fp32_ir", 1, "f64")), n=10007)
