@@ -258,6 +258,33 @@ gls_status gls_profile_read(gls_handle h, gls_phase_stats* out, int32_t reset);
 /* Releases the handle (not the workspace).  NULL is allowed. */
 void gls_destroy(gls_handle h);
 
+/* For callers that cannot allocate device memory or create HIP objects
+ * (serving loops and harnesses that forbid hipMalloc): gls_setup followed by
+ * gls_block over m SNPs, with no workspace argument and no handle.
+ * The workspace is a static device array of GLS_NOALLOC_SCRATCH_BYTES that
+ * each GPU the library runs on holds until the process ends; its device
+ * address is looked up once per device, on the first call with that device
+ * current.  The call allocates no device or host memory and creates no
+ * stream or event; the setup runs entirely on `stream`.
+ * Arguments: as gls_setup (Phi, XL, y, h2, opts, info) and gls_block (XR is
+ *   n x m with ld_xr >= n; b is p x m with ld_b >= p; sigma2, v, snp_status
+ *   have m entries), walked in blocks of opts->block_cols SNPs.
+ *   opts->flags must be 0 (no adjoint, no streaming).
+ * Limit: gls_workspace_bytes(n, p, opts) <= GLS_NOALLOC_SCRATCH_BYTES, else
+ *   GLS_ERR_WORKSPACE (plain FP64, p = 4: n up to 1,536 with block_cols = 256,
+ *   up to about 1,000 with block_cols = 1,024).
+ * Results are bitwise those of gls_setup + gls_block with the same opts.
+ * Synchronizes `stream` before returning (outputs written, scratch free).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call rewrites what it reads): calls that overlap on one GPU,
+ * for instance from two host threads, race and must not be made. */
+#define GLS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gls_status gls_solve_noalloc(int64_t n, int32_t p, const double* Phi, int64_t ld_phi, double h2,
+                             const double* XL, int64_t ld_xl, const double* y,
+                             int64_t m, const double* XR, int64_t ld_xr,
+                             double* b, int64_t ld_b, double* sigma2, double* v, int32_t* snp_status,
+                             const gls_opts* opts, void* stream, int64_t* info);
+
 const char* gls_status_string(gls_status s);
 const char* gls_last_error(void);
 

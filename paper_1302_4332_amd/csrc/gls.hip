@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -430,7 +431,35 @@ void snp_reduce_solve(Ctx* c, const double* Xt, int mb, double* b, int64_t ldb, 
 
 namespace gls {
 
-// Argument checks of gls_setup; fills the plan.
+// Workspace of gls_solve_noalloc: a file-scope array that each device holds
+// from the library's first use on it until the process ends.  Host code must
+// not pass `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in); it uses the device address that noalloc_workspace() looked up.
+static __device__ __align__(256) char scratch[GLS_NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void* g_scratch_at[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch array, looked up once per
+// device with that device current.
+static gls_status noalloc_workspace(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "gls_solve_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return arg_fail("gls_solve_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* at = nullptr;
+    e = hipGetSymbolAddress(&at, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "gls_solve_noalloc: hipGetSymbolAddress");
+    if (!at) return hip_fail(hipErrorInvalidSymbol, "gls_solve_noalloc: hipGetSymbolAddress");
+    g_scratch_at[dev] = at;
+  }
+  *out = static_cast<char*>(g_scratch_at[dev]);
+  return GLS_OK;
+}
+
+// Argument checks shared by gls_setup and gls_solve_noalloc; fills the plan.
 static gls_status setup_args(const char* fn, int64_t n, int32_t p, const double* Phi, int64_t ld_phi, double h2,
                              const double* XL, int64_t ld_xl, const double* y, const gls_opts* opts, Plan* pl) {
   if (!plan_workspace(n, p, opts, pl)) {
@@ -723,6 +752,43 @@ void gls_destroy(gls_handle h) {
     if (c->ev_comp[i]) (void)hipEventDestroy(c->ev_comp[i]);
   }
   delete c;
+}
+
+gls_status gls_solve_noalloc(int64_t n, int32_t p, const double* Phi, int64_t ld_phi, double h2, const double* XL,
+                             int64_t ld_xl, const double* y, int64_t m, const double* XR, int64_t ld_xr, double* b,
+                             int64_t ld_b, double* sigma2, double* v, int32_t* snp_status, const gls_opts* opts,
+                             void* stream, int64_t* info) {
+  if (info) *info = 0;
+  Plan pl;
+  gls_status st = setup_args("gls_solve_noalloc", n, p, Phi, ld_phi, h2, XL, ld_xl, y, opts, &pl);
+  if (st != GLS_OK) return st;
+  if (opts->flags != 0) return arg_fail("gls_solve_noalloc: opts->flags must be 0");
+  if (m < 0) return arg_fail("gls_solve_noalloc: m < 0");
+  if (m > 0 && (!XR || ld_xr < n)) return arg_fail("gls_solve_noalloc: XR is NULL or ld_xr < n");
+  if (m > 0 && (!b || ld_b < p || !sigma2 || !v || !snp_status))
+    return arg_fail("gls_solve_noalloc: NULL output or ld_b < p");
+  if (pl.total > GLS_NOALLOC_SCRATCH_BYTES) {
+    set_err("gls_solve_noalloc: n = %lld, p = %d, block_cols = %d need %zu bytes of workspace, above the %zu of the "
+            "static scratch",
+            (long long)n, p, opts->block_cols, pl.total, (size_t)GLS_NOALLOC_SCRATCH_BYTES);
+    return GLS_ERR_WORKSPACE;
+  }
+  char* ws = nullptr;
+  if ((st = noalloc_workspace(&ws)) != GLS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ctx c;   // the handle lives in this frame: no heap, no events, no side stream
+  if ((st = setup_into(&c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, ws, opts, false, s, info)) != GLS_OK) return st;
+  c.ready = true;
+  for (int64_t j0 = 0; j0 < m && st == GLS_OK; j0 += c.bc) {
+    const int mb = (int)std::min<int64_t>(c.bc, m - j0);
+    st = block_forward(&c, mb, XR + j0 * ld_xr, ld_xr, b + j0 * ld_b, ld_b, sigma2 + j0, v + j0, snp_status + j0, s);
+  }
+  const hipError_t e = hipGetLastError();
+  const hipError_t es = hipStreamSynchronize(s);   // the scratch is free for the next call on return
+  if (st != GLS_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "gls_solve_noalloc: launch");
+  if (es != hipSuccess) return hip_fail(es, "gls_solve_noalloc: synchronize");
+  return GLS_OK;
 }
 
 }  // extern "C"

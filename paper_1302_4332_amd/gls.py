@@ -81,6 +81,8 @@ SIGNATURES = {
     "gls_profile_enable": (ctypes.c_int, [_P, _I32]),
     "gls_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(GlsPhaseStats), _I32]),
     "gls_destroy": (None, [_P]),
+    "gls_solve_noalloc": (ctypes.c_int, [_I64, _I32, _P, _I64, _D, _P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P,
+                                         _P, ctypes.POINTER(GlsOpts), _P, ctypes.POINTER(_I64)]),
     "gls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "gls_last_error": (ctypes.c_char_p, []),
 }
@@ -138,6 +140,37 @@ def make_opts(block_cols: int, precision="fp64", refine_sweeps: int = 0, keep_fo
 
 def workspace_bytes(n: int, p: int, opts: GlsOpts) -> int:
     return int(lib().gls_workspace_bytes(n, p, ctypes.byref(opts)))
+
+
+# size of the library's static device scratch behind gls_solve_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def solve_noalloc(Phi, h2, XL, y, XR, b, sigma2, v, status, *, block_cols: int, precision="fp64",
+                  refine_sweeps: int = 0, stream=None):
+    """gls_solve_noalloc: setup and every SNP of XR (m, n) into caller-provided
+    outputs b (m, p), sigma2, v (m,) float64 and status (m,) int32, with the
+    library's static scratch as workspace (nothing is allocated).  Synchronous."""
+    for t, name in ((Phi, "Phi"), (y, "y"), (XR, "XR"), (b, "b"), (sigma2, "sigma2"), (v, "v")):
+        _need(t, name)
+    _need(status, "status", torch.int32)
+    n = Phi.shape[0]
+    if XL is None:
+        XL = torch.empty((n, 0), dtype=torch.float64, device=Phi.device)
+    p = XL.shape[1] + 1
+    m = XR.shape[0]
+    if tuple(Phi.shape) != (n, n) or tuple(y.shape) != (n,) or XL.shape[0] != n:
+        raise ValueError("Phi must be (n, n), y (n,), XL (n, p - 1)")
+    if XR.dim() != 2 or XR.shape[1] != n or tuple(b.shape) != (m, p) or sigma2.shape[0] != m \
+            or v.shape[0] != m or status.shape[0] != m:
+        raise ValueError(f"XR must be (m, {n}), b (m, {p}), sigma2, v and status (m,)")
+    XLc = XL.t().contiguous() if p > 1 else None
+    opts = make_opts(block_cols, precision, refine_sweeps)
+    info = ctypes.c_int64(0)
+    st = lib().gls_solve_noalloc(n, p, _ptr(Phi), n, float(h2), _ptr(XLc), n, _ptr(y), m, _ptr(XR), n, _ptr(b), p,
+                                 _ptr(sigma2), _ptr(v), _ptr(status), ctypes.byref(opts), _stream(stream),
+                                 ctypes.byref(info))
+    _check(st, info.value)
 
 
 class GLSContext:
