@@ -62,6 +62,13 @@ struct GemmArgs {
   int map_desc;
   int map_gm, map_gn;
   int map_slab;   // 1: column groups outer (a slab of GN column tiles meets every row tile in turn)
+  // trmm_f64_dma_kernel only: with red_q > 0, C is not stored; instead each
+  // row tile ti writes, for every column j, the red_q sums over its rows
+  // sum_i C[i,j] red_W[i + q ld_red_W] (q < red_q - 1) and sum_i C[i,j]^2
+  // (q = red_q - 1) to red_part[(ti red_q + q) ncols + j]
+  const double* red_W; int64_t ld_red_W;
+  double* red_part;
+  int red_q;
 };
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }

@@ -42,6 +42,7 @@ void trmm_f64_dma_kernel(GemmArgs g) {
   constexpr int ASZ = BM * BK * 8, BSZ = BN * BK * 8, STAGE = ASZ + BSZ;
   constexpr int AINS = ASZ / 1024;   // load instructions of A per stage, one k-column each
   static_assert(BM == 128 && BK == 16 && FC == 4 && AINS == 2 * NW && BSZ == NW * 1024, "tile split");
+  static_assert(2 * 21 * BN * 8 <= NS * STAGE, "the ring holds the fused sums (p + 1 <= 21)");
   __shared__ __align__(1024) char smem[NS * STAGE];
 
   int ti, tj;
@@ -129,6 +130,38 @@ void trmm_f64_dma_kernel(GemmArgs g) {
   }
 
   // lane holds C[4 ((lane >> 2) & 3) + (lane >> 4)][lane & 3] of each 16 x 4 slice
+  if (g.red_q > 0) {
+    // Per-column sums over this tile's rows instead of C: each lane sums its four rows (a ascending), a
+    // butterfly over the sixteen lanes of a column adds those (every lane ends with the same sum), and the
+    // two row-strip waves are added in the order wm = 0, 1.  The order depends only on the tile, so every
+    // column's sums are independent of the block's width and of the column's place in it.
+    __syncthreads();   // every wave is done with the ring, which now holds the two strips' sums
+    double* red = reinterpret_cast<double*>(smem);   // [wm][q][64 columns]
+    for (int q = 0; q < g.red_q; ++q) {
+      const bool norm = q == g.red_q - 1;
+      double w[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        w[a] = norm ? 0.0 : g.red_W[(int64_t)(i0 + wm * 64 + a * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4)) +
+                                   (int64_t)q * g.ld_red_W];
+#pragma unroll
+      for (int c = 0; c < FC; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) t += acc[a][c] * (norm ? acc[a][c] : w[a]);
+#pragma unroll
+        for (int off = 4; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
+        if (lane < 4) red[(wm * g.red_q + q) * BN + wn * WTN + c * 4 + lane] = t;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < g.red_q * BN; e += DB_THREADS) {
+      const int q = e / BN, jl = e % BN;
+      if (j0 + jl < g.ncols)
+        g.red_part[(int64_t)(ti * g.red_q + q) * g.ncols + j0 + jl] = red[q * BN + jl] + red[(g.red_q + q) * BN + jl];
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int i = i0 + wm * 64 + a * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);

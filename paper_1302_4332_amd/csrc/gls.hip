@@ -196,14 +196,18 @@ static void gemm_map(bool ta, bool tb, const GemmArgs& g, hipStream_t s) {
   else launch_gemm_cfg<true, true, MAP, VEC>(g, s);
 }
 
+// The direct-load kernel for a product it takes (false: not launched).
+static bool gemm_dma(const GemmArgs& g, hipStream_t s) {
+  if (!trmm_dma_ok(g)) return false;
+  GemmArgs d = g;
+  const int Mt = (g.M + DB_BM - 1) / DB_BM, Nt = (g.ncols + DB_BN - 1) / DB_BN;
+  d.M = Mt * DB_BM;   // rows past mvalid are computed from A's padding and not stored
+  hipLaunchKernelGGL(trmm_f64_dma_kernel, dim3(XcdMap::grid(d, Mt, Nt)), dim3(DB_THREADS), 0, s, d);
+  return true;
+}
+
 void gemm(bool ta, bool tb, bool xcd_map, const GemmArgs& g, hipStream_t s) {
-  if (!ta && !tb && xcd_map && trmm_dma_ok(g)) {
-    GemmArgs d = g;
-    const int Mt = (g.M + DB_BM - 1) / DB_BM, Nt = (g.ncols + DB_BN - 1) / DB_BN;
-    d.M = Mt * DB_BM;   // rows past mvalid are computed from A's padding and not stored
-    hipLaunchKernelGGL(trmm_f64_dma_kernel, dim3(XcdMap::grid(d, Mt, Nt)), dim3(DB_THREADS), 0, s, d);
-    return;
-  }
+  if (!ta && !tb && xcd_map && g.red_q == 0 && gemm_dma(g, s)) return;
   const bool vec = gemm_vec_ok(g, ta, tb);
   if (xcd_map) {
     if (vec) gemm_map<MAP_XCD, true>(ta, tb, g, s);
@@ -401,6 +405,43 @@ void whiten_fp64(Ctx* c, const double* X, int64_t ldx, int mb, int K, int rows, 
   g.a_diag = 0;
   g.map_desc = 1;
   gemm(false, false, true, g, s);
+}
+
+// The same product with the per-SNP sums fused into its epilogue: instead of
+// X~, c->Xt receives for each 128-row tile t and SNP j the sums of x~ times
+// [X~_L | y~] and of x~^2 over the tile's rows ((t (p + 1) + q) mb + j).
+// Returns false, launching nothing, when the direct-load kernel does not
+// take the shape.
+static bool whiten_fp64_fused(Ctx* c, const double* X, int64_t ldx, int mb, int K, int rows, hipStream_t s) {
+  GemmArgs g = gemm_args(c->Linv, c->N, X, ldx, c->Xt, c->N, rows, mb, K, 1.0);
+  g.a_tri = TRI_LOWER;
+  g.a_diag = 0;
+  g.map_desc = 1;
+  g.red_W = c->W;
+  g.ld_red_W = c->N;
+  g.red_part = c->Xt;
+  g.red_q = c->p + 1;
+  return gemm_dma(g, s);
+}
+
+template <int P>
+static void launch_snp_partials_p(Ctx* c, int Mt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(snp_partials_solve_kernel<P>, dim3((mb + 255) / 256), dim3(256), 0, s, c->Xt, Mt, mb, c->small,
+                     (int)c->n, b, ldb, s2, v, st);
+}
+
+static void snp_partials_solve(Ctx* c, int Mt, int mb, double* b, int64_t ldb, double* s2, double* v, int* st,
+                               hipStream_t s) {
+  switch (c->p) {
+#define GLS_P_CASE(P) \
+  case P: launch_snp_partials_p<P>(c, Mt, mb, b, ldb, s2, v, st, s); break;
+    GLS_P_CASE(1) GLS_P_CASE(2) GLS_P_CASE(3) GLS_P_CASE(4) GLS_P_CASE(5) GLS_P_CASE(6) GLS_P_CASE(7)
+    GLS_P_CASE(8) GLS_P_CASE(9) GLS_P_CASE(10) GLS_P_CASE(11) GLS_P_CASE(12) GLS_P_CASE(13) GLS_P_CASE(14)
+    GLS_P_CASE(15) GLS_P_CASE(16) GLS_P_CASE(17) GLS_P_CASE(18) GLS_P_CASE(19) GLS_P_CASE(20)
+#undef GLS_P_CASE
+    default: break;
+  }
 }
 
 template <int P>
@@ -949,13 +990,22 @@ gls_status block_forward(Ctx* c, int mb, const double* XR, int64_t ld_xr, double
       lp_solve(c, c->R, c->N, mb, 1.0, s);
     }
   } else {
-    PhaseTimer t(c, PH_WHITEN, s);
-    int K = 0;
-    const double* X = fp64_operand(c, XR, &ld_xr, mb, &K, s);
-    // the per-SNP sums read rows < n, the residual rows < n rounded up to 16:
-    // row tiles wholly past n are not computed
+    // Plain FP64: the per-SNP sums are fused into the product's epilogue, so
+    // X~ is neither stored nor read back; row tiles wholly past the last
+    // sample are not computed (their rows would only add zeros).
     const int rows = (int)((c->n + DB_BM - 1) / DB_BM * DB_BM);
-    whiten_fp64(c, X, ld_xr, mb, K, rows, c->Xt, s);
+    bool fused;
+    {
+      PhaseTimer t(c, PH_WHITEN, s);
+      int K = 0;
+      const double* X = fp64_operand(c, XR, &ld_xr, mb, &K, s);
+      fused = whiten_fp64_fused(c, X, ld_xr, mb, K, rows, s);
+      if (!fused) whiten_fp64(c, X, ld_xr, mb, K, rows, c->Xt, s);
+    }
+    PhaseTimer t(c, PH_SNP, s);
+    if (fused) snp_partials_solve(c, rows / DB_BM, mb, b, ld_b, s2, v, st, s);
+    else snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
+    return GLS_OK;
   }
   {
     PhaseTimer t(c, PH_SNP, s);

@@ -67,28 +67,34 @@ template <> struct LpMfma<__bf16> {
 };
 
 // Tiles of 256 rows of A x 128 columns of B; eight waves, each a 64 x 64
-// block (4 x 4 accumulators of 16 x 16).  Each stage covers 128 bytes of k per
-// row (64 FP16/BF16 or 32 FP32 values); the 256 + 128 rows of a stage move
-// straight from global memory into a ring of three LDS buffers (1 KB, eight
-// rows, per wave instruction; two stages in flight ahead of the MFMAs).
-// Chunk c of LDS row r sits in slot c ^ lp_swz(r): eight consecutive lanes of a
-// fragment read fall on distinct 128-byte bank lines, sixteen on distinct
-// 256-byte lines.  The product is formed transposed (B's columns as the
+// block (4 x 4 accumulators of 16 x 16).  Each stage covers 64 bytes of k per
+// row (32 FP16/BF16 or 16 FP32 values); the 256 + 128 rows of a stage move
+// straight from global memory into a ring of three LDS buffers (1 KB, sixteen
+// rows, per wave instruction; two stages in flight ahead of the MFMAs).  A
+// stage is 24 KB, so two workgroups share a compute unit (four waves per
+// SIMD, 102 VGPRs); with 128-byte stages (48 KB, one workgroup and two waves
+// per SIMD) the same MFMA sequence ran 9-12% slower.  Chunk c of LDS row r sits
+// in slot c ^ lp_swz(r): eight consecutive lanes of a fragment read fall on
+// distinct banks.  The product is formed transposed (B's columns as the
 // instruction's first operand) so that the FP64 stores of C run down columns.
-// Requires 16-byte aligned A and B, lda and ldb multiples of 8 elements and K
-// a multiple of 64 (the callers pad every operand to N, a multiple of 256).
-constexpr int LP_BM = 256, LP_BN = 128, LP_RB = 128, LP_THREADS = 512, LP_STAGES = 3;
+// Requires 16-byte aligned A and B, lda and ldb multiples of 8 elements, K a
+// multiple of 32 and lane offsets within a tile below 2^32 bytes (the callers
+// pad every operand to N, a multiple of 256).
+constexpr int LP_BM = 256, LP_BN = 128, LP_RB = 64, LP_THREADS = 512, LP_STAGES = 3;
 
-__device__ __forceinline__ int lp_swz(int r) { return (r ^ (r >> 3)) & 7; }
+__device__ __forceinline__ int lp_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
 template <typename T>
-__global__ __launch_bounds__(LP_THREADS) void lp_gemm_kernel(LpArgs g) {
+__global__ __launch_bounds__(LP_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void lp_gemm_kernel(LpArgs g) {
   constexpr int BM = LP_BM, BN = LP_BN, RB = LP_RB, NW = LP_THREADS / 64, NS = LP_STAGES;
+  constexpr int CPR = RB / 16;               // 16-byte chunks per LDS row
+  constexpr int RPI = 1024 / RB;             // rows per 1 KB load instruction
   constexpr int BKE = RB / (int)sizeof(T);   // k per stage
   constexpr int STAGE = (BM + BN) * RB;      // bytes
-  constexpr int NLD = (BM + BN) / 8 / NW;    // load instructions per wave and stage
-  static_assert(NLD * 8 * NW == BM + BN && BM == 4 * 64 && BN == 2 * 64 && NW == 8, "tile split");
-  static_assert(NS * STAGE <= 160 * 1024, "LDS");
+  constexpr int NLD = (BM + BN) / RPI / NW;  // load instructions per wave and stage
+  static_assert(NLD * RPI * NW == BM + BN && BM % RPI == 0 && BM == 4 * 64 && BN == 2 * 64 && NW == 8, "tile split");
+  static_assert(RB == 64 && NS * STAGE <= 80 * 1024, "two workgroups per compute unit");
   __shared__ __align__(1024) char smem[NS * STAGE];
 
   int ti, tj;
@@ -103,24 +109,27 @@ __global__ __launch_bounds__(LP_THREADS) void lp_gemm_kernel(LpArgs g) {
   const int i0 = ti * BM, j0 = tj * BN;
   const int khi = (i0 + BM < g.K) ? i0 + BM : g.K;   // A lower triangular
   const int nk = (khi + BKE - 1) / BKE;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wi = wave & 3, wj = wave >> 2;
-  const char* A = static_cast<const char*>(g.A);
-  const char* B = static_cast<const char*>(g.B);
 
-  // loader: instruction q of this wave fills stage rows 8 (q NW + wave) .. +7
-  // (rows < BM: A's rows i0.., then B's columns j0..; columns past the end read
-  // the last valid one, whose results are dropped)
-  const char* src[NLD];
+  // loader: instruction q of this wave fills stage rows RPI (q NW + wave) ..
+  // + RPI - 1, all of A's tile (rows i0..) or all of B's (columns j0..; columns
+  // past the end read the last valid one, whose results are dropped); a
+  // wave-uniform base per operand plus a 32-bit byte offset per lane
+  const char* Abase = static_cast<const char*>(g.A) + (int64_t)i0 * g.lda * (int64_t)sizeof(T);
+  const char* Bbase = static_cast<const char*>(g.B) + (int64_t)j0 * g.ldb * (int64_t)sizeof(T);
+  uint32_t voff[NLD];
 #pragma unroll
   for (int q = 0; q < NLD; ++q) {
-    const int r = 8 * (q * NW + wave) + (lane >> 3);
-    const int chunk = (lane & 7) ^ lp_swz(r);
-    if (r < BM) {
-      src[q] = A + ((int64_t)(i0 + r) * g.lda) * (int64_t)sizeof(T) + 16 * chunk;
+    const int r0 = RPI * (q * NW + wave);
+    const int r = r0 + lane / CPR;
+    const int chunk = (lane % CPR) ^ lp_swz(r);
+    if (r0 < BM) {
+      voff[q] = (uint32_t)((int64_t)r * g.lda * (int64_t)sizeof(T) + 16 * chunk);
     } else {
-      const int j = min(j0 + r - BM, g.ncols - 1);
-      src[q] = B + ((int64_t)j * g.ldb) * (int64_t)sizeof(T) + 16 * chunk;
+      const int jl = min(j0 + r - BM, g.ncols - 1) - j0;
+      voff[q] = (uint32_t)((int64_t)jl * g.ldb * (int64_t)sizeof(T) + 16 * chunk);
     }
   }
   const uint32_t lds0 = lds_address(smem);
@@ -129,20 +138,17 @@ __global__ __launch_bounds__(LP_THREADS) void lp_gemm_kernel(LpArgs g) {
     const int64_t kb = (int64_t)kstep * RB;
 #pragma unroll
     for (int q = 0; q < NLD; ++q)
-      lds_load16(src[q] + kb, __builtin_amdgcn_readfirstlane(base + 1024 * (q * NW + wave)));
+      lds_load16_sv((RPI * (q * NW + wave) < BM ? Abase : Bbase) + kb, voff[q], base + 1024 * (q * NW + wave));
   };
 
-  // fragment offsets within a stage: span h (64 bytes of k), lane group lane >> 4
-  int offa[4][2], offb[4][2];
+  // fragment offsets within a stage: lane group lane >> 4 reads chunk lane >> 4 of its row
+  int offa[4], offb[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     const int ra = wi * 64 + f * 16 + (lane & 15), rb = BM + wj * 64 + f * 16 + (lane & 15);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int c = 4 * h + (lane >> 4);
-      offa[f][h] = ra * RB + 16 * (c ^ lp_swz(ra));
-      offb[f][h] = rb * RB + 16 * (c ^ lp_swz(rb));
-    }
+    const int c = lane >> 4;
+    offa[f] = ra * RB + 16 * (c ^ lp_swz(ra));
+    offb[f] = rb * RB + 16 * (c ^ lp_swz(rb));
   }
 
   f4_t acc[4][4];   // [column block][row block], transposed 16 x 16 products
@@ -158,19 +164,16 @@ __global__ __launch_bounds__(LP_THREADS) void lp_gemm_kernel(LpArgs g) {
     __syncthreads();                              // ... and every wave's; stage (it - 1) % NS is free
     if (it + NS - 1 < nk) issue(it + NS - 1);
     const char* st = smem + (it % NS) * STAGE;
+    uint4 fa[4], fb[4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      uint4 fa[4], fb[4];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        fa[f] = *reinterpret_cast<const uint4*>(st + offa[f][h]);
-        fb[f] = *reinterpret_cast<const uint4*>(st + offb[f][h]);
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) acc[b][a] = LpMfma<T>::mma(fb[b], fa[a], acc[b][a]);
+    for (int f = 0; f < 4; ++f) {
+      fa[f] = *reinterpret_cast<const uint4*>(st + offa[f]);
+      fb[f] = *reinterpret_cast<const uint4*>(st + offb[f]);
     }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[b][a] = LpMfma<T>::mma(fb[b], fa[a], acc[b][a]);
   }
 
   // acc[b][a][t] = C[i0 + wi 64 + 16 a + lane % 16][j0 + wj 64 + 16 b + 4 (lane / 16) + t]

@@ -140,4 +140,35 @@ void snp_reduce_solve_kernel(const double* __restrict__ Xt, int64_t ldx, int N, 
   }
 }
 
+// The per-SNP solve from row-tile partial sums (the product's fused epilogue):
+// part[(t (P + 1) + q) mb + j] for row tiles t < Mt holds SNP j's sums over
+// tile t of x~ times [X~_L | y~] column q (q < P) and of x~^2 (q = P).  One
+// thread per SNP adds the tiles in order, then solves as snp_reduce_solve_kernel.
+template <int P>
+__global__ __launch_bounds__(256) void snp_partials_solve_kernel(const double* __restrict__ part, int Mt, int mb,
+                                                                  const double* __restrict__ small, int n,
+                                                                  double* __restrict__ b, int64_t ldb,
+                                                                  double* __restrict__ sigma2, double* __restrict__ v,
+                                                                  int* __restrict__ status) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= mb) return;
+  double sv[P + 1];
+#pragma unroll
+  for (int q = 0; q <= P; ++q) sv[q] = 0.0;
+  for (int t = 0; t < Mt; ++t) {
+    const double* pt = part + (int64_t)t * (P + 1) * mb + j;
+#pragma unroll
+    for (int q = 0; q <= P; ++q) sv[q] += pt[(int64_t)q * mb];
+  }
+  double bo[P];
+  double s2, vv;
+  int st;
+  snp_solve<P>(small, sv, sv[P - 1], sv[P], n, bo, &s2, &vv, &st);
+#pragma unroll
+  for (int q = 0; q < P; ++q) b[(int64_t)j * ldb + q] = bo[q];
+  sigma2[j] = s2;
+  v[j] = vv;
+  status[j] = st;
+}
+
 }  // namespace gls
