@@ -171,36 +171,51 @@ void snp_adjoint_kernel(double* __restrict__ Xt, int64_t ldx, int N, int mb, con
   ct[t] = kappa;
 }
 
-// acc[t] += sum over SNPs j < mb of contrib[t + j * nc]; workgroup t, each
-// thread a strided share of the SNPs, then a fixed-order tree (deterministic).
+// Study-wide adjoint sums add the block's SNPs in groups of 16 consecutive
+// SNPs: each group is summed in SNP order, and the group sums are added to the
+// running value in group order.  With blocks that start at multiples of 16
+// the groups and their order are the same whatever the block widths, so these
+// sums are bitwise independent of how SNPs are grouped into blocks.
+constexpr int ADJ_GROUP = 16;
+constexpr int ADJ_GROUPS_PER_PASS = 1024;   // group sums held in LDS per pass of reduce_contrib_kernel
+
+// acc[t] += the block's contributions contrib[t + j nc], j < mb, one
+// workgroup per term: the group sums in parallel, then one thread adds them.
 __global__ __launch_bounds__(256) void reduce_contrib_kernel(const double* __restrict__ contrib, int nc, int mb,
                                                              double* __restrict__ acc) {
-  __shared__ double red[256];
+  __shared__ double gs[ADJ_GROUPS_PER_PASS];
   const int t = blockIdx.x;
-  double s = 0.0;
-  for (int j = threadIdx.x; j < mb; j += 256) s += contrib[t + (int64_t)j * nc];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+  const int groups = (mb + ADJ_GROUP - 1) / ADJ_GROUP;
+  double run = acc[t];   // meaningful in thread 0
+  for (int g0 = 0; g0 < groups; g0 += ADJ_GROUPS_PER_PASS) {
+    const int gn = min(ADJ_GROUPS_PER_PASS, groups - g0);
+    for (int g = threadIdx.x; g < gn; g += 256) {
+      const int j0 = (g0 + g) * ADJ_GROUP, j1 = min(mb, j0 + ADJ_GROUP);
+      double s = 0.0;
+      for (int j = j0; j < j1; ++j) s += contrib[t + (int64_t)j * nc];
+      gs[g] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int g = 0; g < gn; ++g) run += gs[g];
     __syncthreads();
   }
-  if (threadIdx.x == 0) acc[t] += red[0];
+  if (threadIdx.x == 0) acc[t] = run;
 }
 
-// Partial sums of Wbar += X~ Cbar^T (N x P; X~ N x mb, ld N; Cbar P x mb):
-//   part[(q * P + t) * N + r] = sum over SNPs j in chunk q of X~[r, j] Cbar[t, j].
-// Thread r of workgroup (row block, chunk q); rows are coalesced, Cbar is
-// broadcast.  wbar_add_kernel then adds the `chunks` chunks in order.
+// Wbar += X~ Cbar^T (N x P; X~ N x mb, ld N; Cbar P x mb) in groups of 16
+// SNPs as above, in two steps.  wbar_group_kernel forms the sums of groups
+// g0 .. g0 + gn - 1, one thread per (row r, group):
+//   part[(g P + t) N + r] = sum over the group's SNPs j, in order, of X~[r, j] Cbar[t, j]
+// (rows coalesced, Cbar broadcast); wbar_add_kernel then adds them to Wbar in
+// group order, one thread per entry of Wbar.
 template <int P>
-__global__ __launch_bounds__(256) void wbar_partial_kernel(const double* __restrict__ Xt, int N, int mb, int chunks,
-                                                           const double* __restrict__ Cbar,
-                                                           double* __restrict__ part) {
+__global__ __launch_bounds__(256) void wbar_group_kernel(const double* __restrict__ Xt, int N, int mb, int g0,
+                                                         const double* __restrict__ Cbar, double* __restrict__ part) {
   const int r = blockIdx.x * 256 + threadIdx.x;
-  const int q = blockIdx.y;
+  const int g = blockIdx.y;
   if (r >= N) return;
-  const int per = (mb + chunks - 1) / chunks;
-  const int j0 = q * per, j1 = min(mb, j0 + per);
+  const int j0 = (g0 + g) * ADJ_GROUP, j1 = min(mb, j0 + ADJ_GROUP);
   double s[P];
 #pragma unroll
   for (int t = 0; t < P; ++t) s[t] = 0.0;
@@ -210,17 +225,17 @@ __global__ __launch_bounds__(256) void wbar_partial_kernel(const double* __restr
     for (int t = 0; t < P; ++t) s[t] += x * Cbar[t + (int64_t)j * P];
   }
 #pragma unroll
-  for (int t = 0; t < P; ++t) part[((int64_t)q * P + t) * N + r] = s[t];
+  for (int t = 0; t < P; ++t) part[((int64_t)g * P + t) * N + r] = s[t];
 }
 
-// Wbar[r + t N] += sum over chunks q, in order, of part[(q * P + t) * N + r].
-__global__ void wbar_add_kernel(const double* __restrict__ part, int N, int P, int chunks, double* __restrict__ Wbar) {
+__global__ void wbar_add_kernel(const double* __restrict__ part, int N, int P, int gn, double* __restrict__ Wbar) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)N * P) return;
   const int r = (int)(idx % N), t = (int)(idx / N);
-  double s = 0.0;
-  for (int q = 0; q < chunks; ++q) s += part[((int64_t)q * P + t) * N + r];
-  Wbar[idx] += s;
+  double run = Wbar[idx];
+#pragma unroll 8
+  for (int g = 0; g < gn; ++g) run += part[((int64_t)g * P + t) * N + r];
+  Wbar[idx] = run;
 }
 
 // Xtbar[r, j] = sum_t W[r, t] Cbar[t, j] + ebar[j] Xt[r, j]   (N x mb, ld N)

@@ -69,6 +69,11 @@ struct GemmArgs {
   const double* red_W; int64_t ld_red_W;
   double* red_part;
   int red_q;
+  // trmm_f64_dma_kernel only: with acc_cin (alpha = +-1, beta = 1) the
+  // accumulators start at alpha Cin and C = alpha acc: the k stages add onto
+  // the running value in order, so a sum split over launches at stage
+  // boundaries gives bitwise the result of one launch
+  int acc_cin;
 };
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }

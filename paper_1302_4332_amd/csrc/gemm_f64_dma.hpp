@@ -50,9 +50,12 @@ void trmm_f64_dma_kernel(GemmArgs g) {
   if (!XcdMap::tile(g, blockIdx.x, Mt, Nt, &ti, &tj)) return;
   const int i0 = ti * BM, j0 = tj * BN;
   if (g.c_lower && (i0 + BM - 1) < (j0 + g.c_diag)) return;   // a tile wholly above the lower part
+  // k range of the tile: a lower-triangular A ends at the tile's last row, an upper-triangular one starts at its
+  // first (both hold explicit zeros across the diagonal block)
   int khi = g.K;
-  if (g.a_tri == TRI_LOWER) khi = imin(khi, i0 + BM + g.a_diag);
+  if (g.a_tri == TRI_LOWER) khi = imin(khi, i0 + BM);
   const int nk = (khi + BK - 1) / BK;
+  const int k0 = (g.a_tri == TRI_UPPER) ? i0 / BK : 0;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WGM, wn = wave / WGM;
@@ -90,6 +93,17 @@ void trmm_f64_dma_kernel(GemmArgs g) {
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < FC; ++c) acc[a][c] = 0.0;
+  if (g.acc_cin) {   // start from alpha Cin (alpha = +-1: exact)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + wm * 64 + a * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+#pragma unroll
+      for (int c = 0; c < FC; ++c) {
+        const int j = j0 + wn * WTN + c * 4 + (lane & 3);
+        if (i < g.mvalid && j < g.ncols) acc[a][c] = g.alpha * g.Cin[(int64_t)i + (int64_t)j * g.ldcin];
+      }
+    }
+  }
 
   // k order within a stage: MFMA s sums k = 4 (lane / 16) + s over the four lane groups (a permutation of the
   // stage's 16 k that both operands share), so a lane's four B values of a column are adjacent: two 16-byte reads
@@ -98,8 +112,8 @@ void trmm_f64_dma_kernel(GemmArgs g) {
   const int g4 = 4 * (lane >> 4);
   const int abase = g4 * (8 * BM) + wm * 512 + ((lane & 15) >> 1) * 16 + (lane & 1) * 8;
 
-  if (nk > 0) issue(0);
-  for (int it = 0; it < nk; ++it) {
+  if (k0 < nk) issue(k0);
+  for (int it = k0; it < nk; ++it) {
     wait_vmcnt<0>();   // this wave's loads of stage it have landed ...
     __syncthreads();   // ... and every wave's; the other stage is free
     if (it + 1 < nk) issue(it + 1);
@@ -171,22 +185,22 @@ void trmm_f64_dma_kernel(GemmArgs g) {
       const int j = j0 + wn * WTN + c * 4 + (lane & 3);
       if (j >= g.ncols) continue;
       double val = g.alpha * acc[a][c];
-      if (g.beta != 0.0) val += g.beta * g.Cin[(int64_t)i + (int64_t)j * g.ldcin];
+      if (g.beta != 0.0 && !g.acc_cin) val += g.beta * g.Cin[(int64_t)i + (int64_t)j * g.ldcin];
       g.C[(int64_t)i + (int64_t)j * g.ldc] = val;
     }
   }
 }
 
-// Whether trmm_f64_dma_kernel applies to a product without transposes: no
-// triangular B, 16-byte aligned operands with even leading dimensions,
+// Whether trmm_f64_dma_kernel applies to a product without transposes: A
+// full, lower or upper triangular (diagonal offset 0), no triangular B,
+// 16-byte aligned operands with even leading dimensions,
 // K a multiple of 16, the rows of A up to M rounded up to 128 inside A's
 // leading dimension (they are read; rows past M are not stored), and lane
 // offsets within a stage (15 columns of A, 63 columns of B) below 2^32 bytes.
 inline bool trmm_dma_ok(const GemmArgs& g) {
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   if (!al16(g.A) || !al16(g.B) || (g.lda & 1) || (g.ldb & 1)) return false;
-  if (g.b_tri != TRI_NONE || (g.a_tri != TRI_NONE && g.a_tri != TRI_LOWER)) return false;
-  if (g.a_tri == TRI_LOWER && g.a_diag != 0) return false;
+  if (g.b_tri != TRI_NONE || g.a_diag != 0) return false;
   if (g.M <= 0 || g.K % DB_BK || g.K <= 0 || g.ncols <= 0 || g.mvalid > g.M) return false;
   if (g.lda < (int64_t)(g.M + DB_BM - 1) / DB_BM * DB_BM || g.ldb < g.K) return false;
   if ((15 * g.lda + DB_BM) * 8 >= ((int64_t)1 << 32) || (63 * g.ldb + DB_BK) * 8 >= ((int64_t)1 << 32)) return false;

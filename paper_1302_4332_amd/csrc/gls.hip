@@ -106,7 +106,8 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   pl->off_Linv = take(sizeof(double) * N * N);
   pl->off_W = take(sizeof(double) * N * p);
   // the panel of a recursion node and, for big nodes, its transpose
-  int64_t tmp = std::max<int64_t>(N * bc, 2 * recursion_temp_leaves(0, Kt) * NB_LEAF * NB_LEAF);
+  // the whitened block (N x bc, padded to a multiple of 64 SNPs for the adjoint's zero SNPs), the setup's panels
+  int64_t tmp = std::max<int64_t>(N * ((bc + 63) / 64 * 64), 2 * recursion_temp_leaves(0, Kt) * NB_LEAF * NB_LEAF);
   tmp = std::max<int64_t>(tmp, N * p * (1 + (N + TA_KC - 1) / TA_KC));   // [X_L | y] and its split-k partials
   pl->off_Xt = take(sizeof(double) * tmp);
   {
@@ -1081,6 +1082,10 @@ gls_status block_forward_u2(Ctx* c, int mb, const uint8_t* G2, int64_t ldg, doub
 
 void reset_adjoint(Ctx* c, hipStream_t s) {
   const int64_t N = c->N;
+  // T2 holds (L^-1)^T until the Cholesky adjoint of the pass's finish step reuses it: the per-block
+  // X_R bar = L^-T X~_R bar then reads an upper-triangular A without a transpose (the direct-load product)
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((N + 31) / 32), (unsigned)((N + 31) / 32)), dim3(256), 0, s,
+                     c->T2, N, c->Linv, N, (int)N, (int)N);
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Lbar, N * N, 0.0);
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * c->p)), dim3(256), 0, s, c->Wb, N * c->p, 0.0);
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, s, c->acc, (int64_t)adj_nc(c->p), 0.0);
@@ -1135,44 +1140,52 @@ gls_status block_backward(Ctx* c, int mb, const double* XR, int64_t ld_xr, const
 #define GLS_ADJ(P) adjoint_snp_p<P>(c, mb, bbar, s2bar, vbar, s)
   GLS_P_SWITCH(c->p, GLS_ADJ)
 #undef GLS_ADJ
-  {  // Wbar += X~_R Cbar^T: partial sums over SNP chunks into Xb (free until the next product), then in order
+  {  // Wbar += X~_R Cbar^T in groups of 16 SNPs: group sums into Xb (free until the next product), then added in
+     // group order; as many groups per pass as Xb holds (p columns of N per group)
     const int p = c->p;
-    const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(32, c->plan.bcp / p));
-#define GLS_WP(P)                                                                                                 \
-  hipLaunchKernelGGL(wbar_partial_kernel<P>, dim3((unsigned)((N + 255) / 256), (unsigned)chunks), dim3(256), 0, s, \
-                     c->Xt, (int)N, mb, chunks, c->Cb, c->Xb);
-    GLS_P_SWITCH(p, GLS_WP)
-#undef GLS_WP
-    hipLaunchKernelGGL(wbar_add_kernel, dim3(grid_for(N * p)), dim3(256), 0, s, c->Xb, (int)N, p, chunks, c->Wb);
+    const int groups = (mb + ADJ_GROUP - 1) / ADJ_GROUP;
+    const int per_pass = (int)std::max<int64_t>(1, c->plan.bcp / p);
+    for (int g0 = 0; g0 < groups; g0 += per_pass) {
+      const int gn = std::min(per_pass, groups - g0);
+#define GLS_WG(P)                                                                                                  \
+  hipLaunchKernelGGL(wbar_group_kernel<P>, dim3((unsigned)((N + 255) / 256), (unsigned)gn), dim3(256), 0, s, c->Xt, \
+                     (int)N, mb, g0, c->Cb, c->Xb);
+      GLS_P_SWITCH(p, GLS_WG)
+#undef GLS_WG
+      hipLaunchKernelGGL(wbar_add_kernel, dim3(grid_for(N * p)), dim3(256), 0, s, c->Xb, (int)N, p, gn, c->Wb);
+    }
   }
-  {  // X_R bar = L^-T X~_R bar   (op(A) = (L^-1)^T, upper: non-zero for k >= i)
-    GemmArgs g = gemm_args(c->Linv, N, c->Xtb, N, c->Xb, N, (int)N, mb, (int)N, 1.0);
+  {  // X_R bar = L^-T X~_R bar   (A = (L^-1)^T in T2, upper: non-zero for k >= i; low row tiles hold the most k)
+    GemmArgs g = gemm_args(c->T2, N, c->Xtb, N, c->Xb, N, (int)N, mb, (int)N, 1.0);
     g.a_tri = TRI_UPPER;
     g.a_diag = 0;
     g.map_desc = 0;
-    gemm(true, false, true, g, s);
+    gemm(false, false, true, g, s);
   }
   if (XR_grad)
     hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(c->n * mb)), dim3(256), 0, s, XR_grad, ld_xr, c->Xb, N, (int)c->n,
                        mb);
-  // Lbar -= X_R bar X~_R^T (lower tiles; high row tiles hold the most of them).  With mb a multiple of 16
-  // X~_R^T is formed in Xtb (free once X_R bar is formed) and the product runs on the direct-load kernel.
-  if (mb % 16 == 0) {
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((N + 31) / 32), (unsigned)((mb + 31) / 32)), dim3(256), 0, s,
-                       c->Xtb, (int64_t)mb, c->Xt, N, (int)N, mb);
-    GemmArgs g = gemm_args(c->Xb, N, c->Xtb, mb, c->Lbar, N, (int)N, (int)N, mb, -1.0);
+  // Lbar -= X_R bar X~_R^T (lower tiles; high row tiles hold the most of them) on the direct-load kernel:
+  // X~_R^T is formed in Xtb (free once X_R bar is formed), the SNP count is padded to a multiple of 16 with
+  // zero SNPs, and the accumulators start from -Lbar, so the 16-SNP stages add onto the running Lbar in SNP
+  // order: for block widths that are multiples of 16 Lbar is bitwise independent of the blocking.
+  {
+    const int K16 = (mb + DB_BK - 1) / DB_BK * DB_BK;
+    if (K16 > mb) {
+      hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * (K16 - mb))), dim3(256), 0, s, c->Xt + N * mb,
+                         N * (K16 - mb), 0.0);
+      hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * (K16 - mb))), dim3(256), 0, s, c->Xb + N * mb,
+                         N * (K16 - mb), 0.0);
+    }
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((N + 31) / 32), (unsigned)((K16 + 31) / 32)), dim3(256), 0,
+                       s, c->Xtb, (int64_t)K16, c->Xt, N, (int)N, K16);
+    GemmArgs g = gemm_args(c->Xb, N, c->Xtb, K16, c->Lbar, N, (int)N, (int)N, K16, -1.0);
     g.beta = 1.0;
+    g.acc_cin = 1;
     g.c_lower = 1;
     g.c_diag = 0;
     g.map_desc = 1;
     gemm(false, false, true, g, s);
-  } else {  // op(B)[k][j] = X~[j + k N]
-    GemmArgs g = gemm_args(c->Xb, N, c->Xt, N, c->Lbar, N, (int)N, (int)N, mb, -1.0);
-    g.beta = 1.0;
-    g.c_lower = 1;
-    g.c_diag = 0;
-    g.map_desc = 1;
-    gemm(false, true, true, g, s);
   }
   return GLS_OK;
 }

@@ -174,3 +174,24 @@ def test_adjoint_nan_snp_masked_loss(precision, sweeps):
     _close(gy, ry)
     _close(gX[fin], rX.T)
     assert gh == pytest.approx(rh, rel=TOL_G)
+
+
+@pytest.mark.parametrize("precision,sweeps", [("fp64", 0), ("fp32_ir", 2)])
+def test_adjoint_block_width_bitwise(precision, sweeps):
+    """The study-wide adjoint sums (Lbar, Wbar, the shared terms) add SNPs in
+    SNP order and in 16-SNP stages, so for block widths that are multiples of
+    16 every gradient is bitwise independent of the blocking, ragged last
+    blocks included (200 SNPs in blocks of 200, 112, 64, 48 and 16); the first
+    is also held to the reference bar."""
+    Phi, h2, XL, y, XR = _problem(300, 4, 200, seed=21, h2=0.4)
+    outs = [_gpu_grads(Phi, h2, XL, y, XR, bc, precision, sweeps) for bc in (200, 112, 64, 48, 16)]
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        assert np.array_equal(o[1], outs[0][1]), "y gradient"
+        assert np.array_equal(o[2], outs[0][2]), "X_R gradient"
+        assert o[3] == outs[0][3], "h2 gradient"
+    _, ry, rX, rh = G.loss_and_grads(Phi, h2, XL, y, XR.T)
+    _close(outs[0][1], ry)
+    _close(outs[0][2], rX.T)
+    assert outs[0][3] == pytest.approx(rh, rel=TOL_G)
+
