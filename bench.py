@@ -293,18 +293,21 @@ def measure_scale(args, dev):
     ctx.stream(host[:bc], out=tuple(o[:bc] for o in out))   # warm-up
     torch.cuda.synchronize()
     done, wall_ms, compute_ms, passes = 0, 0.0, 0.0, 0
+    pass_ms = []   # (device wall, summed solve time) per pass: the copies hide under the solves when they agree
     t0 = time.perf_counter()
     while done < w.m:
         k = min(pool, w.m - done)
         _, s_ = ctx.stream(host[:k], out=tuple(o[:k] for o in out))
         wall_ms += s_.wall_ms
         compute_ms += s_.compute_ms
+        pass_ms.append((round(s_.wall_ms, 1), round(s_.compute_ms, 1)))
         done += k
         passes += 1
     total = time.perf_counter() - t0
     ctx.close()
     res = {"workload": w.name, "n": n, "p": p, "m": w.m, "block_cols": bc, "pool_snps": pool, "passes": passes,
            "snps_per_s": w.m / total, "snps_per_s_device_wall": w.m / (wall_ms / 1e3), "compute_ms": compute_ms,
+           "pass_wall_compute_ms": pass_ms,
            "note": "PCIe-inclusive, setup excluded; a pinned pool of distinct SNPs streamed repeatedly"}
     log(f"scale {w.name}: {w.m:,} SNPs in {total:.2f} s -> {w.m / total:,.0f} SNPs/s ({passes} passes)")
     return res

@@ -172,6 +172,11 @@ typedef struct {
  * (block_cols / 8, growing by a quarter per block, multiples of 64), so the
  * first copy, which nothing overlaps, is short; results are bitwise the same
  * for any blocking.
+ * copy_stream NULL (recommended): the handle's own compute and copy streams,
+ * created one after the other at setup so that they sit on different hardware
+ * queues, run the study after the work already queued on compute_stream.  A
+ * caller-given copy stream that shares compute_stream's hardware queue (HIP
+ * multiplexes streams over a few queues) serializes every copy with the solves.
  * Returns after every result has landed.  col0 > 0 resumes an interrupted
  * run: outputs for columns < col0 are not touched.  col0 == m (an empty
  * stream) returns GLS_OK at once, and the pointers may then be NULL. */

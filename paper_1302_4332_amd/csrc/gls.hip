@@ -687,6 +687,14 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
       return hip_fail(e, "gls_setup: event create");
     }
   }
+  // created one right after the other: the runtime gives a new stream its least
+  // used hardware queue, so the pair does not share one
+  if ((e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&c->own_st[0], hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&c->own_st[1], hipStreamNonBlocking)) != hipSuccess) {
+    gls_destroy(c);
+    return hip_fail(e, "gls_setup: stream create");
+  }
   c->ready = true;
   *out = c;
   return GLS_OK;
@@ -789,6 +797,13 @@ void gls_destroy(gls_handle h) {
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2; ++i) {
+    if (c->own_st[i]) {
+      (void)hipStreamSynchronize(c->own_st[i]);
+      (void)hipStreamDestroy(c->own_st[i]);
+    }
+  }
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (int i = 0; i < 2; ++i) {
     if (c->ev_copy[i]) (void)hipEventDestroy(c->ev_copy[i]);
     if (c->ev_comp[i]) (void)hipEventDestroy(c->ev_comp[i]);

@@ -87,6 +87,10 @@ struct gls_ctx {
   double* acc = nullptr;    // nc accumulated shared adjoints, then partial sums
   hipEvent_t ev_copy[2] = {nullptr, nullptr};
   hipEvent_t ev_comp[2] = {nullptr, nullptr};
+  // the handle's own compute and copy streams for streamed studies, and the
+  // event that orders them after the caller's stream
+  hipStream_t own_st[2] = {nullptr, nullptr};
+  hipEvent_t ev_join = nullptr;
   // phase timing (gls_profile_*)
   struct ProfRec {
     int phase;

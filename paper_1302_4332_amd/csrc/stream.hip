@@ -98,14 +98,35 @@ std::vector<int64_t> block_schedule(int64_t bc, int64_t total) {
   return bstart;
 }
 
+// The streams a study runs on.  A caller that passes a copy stream gets its own
+// pair; otherwise the handle's pair runs it, after the work already queued on
+// the caller's compute stream.
+struct RunStreams {
+  hipStream_t sc = nullptr, sx = nullptr;
+};
+
+hipError_t run_streams(Ctx* c, void* compute_stream, void* copy_stream, RunStreams* r) {
+  const hipStream_t caller = static_cast<hipStream_t>(compute_stream);
+  if (copy_stream) {
+    r->sc = caller;
+    r->sx = static_cast<hipStream_t>(copy_stream);
+    return hipSuccess;
+  }
+  r->sc = c->own_st[0];
+  r->sx = c->own_st[1];
+  hipError_t e = hipEventRecord(c->ev_join, caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(r->sc, c->ev_join, 0);
+  if (e == hipSuccess) e = hipStreamWaitEvent(r->sx, c->ev_join, 0);
+  return e;
+}
+
 }  // namespace
 
 template <typename T>
 static gls_status stream_run(gls_handle h, int64_t m, int64_t col0, const T* XR_host, int64_t ld_xr, double* b_host,
-                             double* sigma2_host, double* v_host, int32_t* status_host, void* compute_stream,
-                             void* copy_stream, gls_stream_stats* stats_out) {
+                             double* sigma2_host, double* v_host, int32_t* status_host, RunStreams rs,
+                             gls_stream_stats* stats_out) {
   Ctx* c = h;
-  if (!c || !c->ready) return arg_fail("gls_stream: handle is not set up"), GLS_ERR_STATE;
   if (m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream: need 0 <= col0 <= m");
   if (col0 == m) {   // nothing to stream: no pointer is used
     if (stats_out) *stats_out = gls_stream_stats{};
@@ -114,9 +135,9 @@ static gls_status stream_run(gls_handle h, int64_t m, int64_t col0, const T* XR_
   const int64_t rows = col_elems(c, XR_host);
   if (!XR_host || ld_xr < rows) return arg_fail("gls_stream: the SNP matrix is NULL or its ld is below a column");
   if (!b_host || !sigma2_host || !v_host || !status_host) return arg_fail("gls_stream: NULL host output");
-  hipStream_t sc = static_cast<hipStream_t>(compute_stream);
+  hipStream_t sc = rs.sc;
   // serial mode: every copy on the compute stream, so nothing overlaps
-  hipStream_t sx = (c->opts.flags & GLS_STREAM_SERIAL) ? sc : static_cast<hipStream_t>(copy_stream);
+  hipStream_t sx = (c->opts.flags & GLS_STREAM_SERIAL) ? sc : rs.sx;
   const int64_t bc = c->bc;
   const int p = c->p;
   const std::vector<int64_t> bstart = block_schedule(bc, m - col0);
@@ -208,11 +229,16 @@ template <typename T>
 static gls_status stream_impl(gls_handle h, int64_t m, int64_t col0, const T* XR_host, int64_t ld_xr, double* b_host,
                               double* sigma2_host, double* v_host, int32_t* status_host, void* compute_stream,
                               void* copy_stream, gls_stream_stats* stats_out) {
-  const gls_status r = stream_run(h, m, col0, XR_host, ld_xr, b_host, sigma2_host, v_host, status_host,
-                                  compute_stream, copy_stream, stats_out);
+  Ctx* c = h;
+  if (!c || !c->ready) return arg_fail("gls_stream: handle is not set up"), GLS_ERR_STATE;
+  RunStreams rs;
+  hipError_t e = run_streams(c, compute_stream, copy_stream, &rs);
+  if (e != hipSuccess) return hip_fail(e, "gls_stream: stream order");
+  const gls_status r = stream_run(h, m, col0, XR_host, ld_xr, b_host, sigma2_host, v_host, status_host, rs,
+                                  stats_out);
   if (r != GLS_OK) {
-    (void)hipStreamSynchronize(static_cast<hipStream_t>(compute_stream));
-    (void)hipStreamSynchronize(static_cast<hipStream_t>(copy_stream));
+    (void)hipStreamSynchronize(rs.sc);
+    (void)hipStreamSynchronize(rs.sx);
   }
   return r;
 }
@@ -471,7 +497,13 @@ extern "C" gls_status gls_stream_file(gls_handle h, const char* path, int64_t of
   const int fd = open(path, O_RDONLY);
   if (fd < 0) return arg_fail("gls_stream_file: cannot open the file");
   gls_status st;
-  const hipStream_t sc = static_cast<hipStream_t>(compute_stream), sx = static_cast<hipStream_t>(copy_stream);
+  RunStreams rs;
+  const hipError_t e = run_streams(c, compute_stream, copy_stream, &rs);
+  if (e != hipSuccess) {
+    close(fd);
+    return hip_fail(e, "gls_stream_file: stream order");
+  }
+  const hipStream_t sc = rs.sc, sx = rs.sx;
   char* ring = static_cast<char*>(host_ws);
   if (elem_bits == 64)
     st = stream_file_impl<double>(c, fd, offset, m, col0, ring, b_host, sigma2_host, v_host, status_host, sc, sx,

@@ -324,9 +324,9 @@ class GLSContext:
         b, s2, v, status = out
         stats = GlsStreamStats()
         cs = compute_stream or torch.cuda.current_stream()
-        xs = copy_stream or torch.cuda.Stream()
+        xs = self._use(copy_stream) if copy_stream is not None else ctypes.c_void_p(None)
         st = lib().gls_stream_file(self.handle, path.encode(), offset, elem, m, col0, _ptr(host_ws), host_ws.numel(),
-                                   _ptr(b), _ptr(s2), _ptr(v), _ptr(status), self._use(cs), self._use(xs),
+                                   _ptr(b), _ptr(s2), _ptr(v), _ptr(status), self._use(cs), xs,
                                    ctypes.byref(stats))
         _check(st)
         return (b, s2, v, status), stats
@@ -363,9 +363,9 @@ class GLSContext:
                 raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
         stats = GlsStreamStats()
         cs = compute_stream or torch.cuda.current_stream()
-        xs = copy_stream or torch.cuda.Stream()
+        xs = self._use(copy_stream) if copy_stream is not None else ctypes.c_void_p(None)
         st = entry(self.handle, m, col0, _ptr(XR_host), rowlen, _ptr(b), _ptr(s2), _ptr(v),
-                   _ptr(status), self._use(cs), self._use(xs), ctypes.byref(stats))
+                   _ptr(status), self._use(cs), xs, ctypes.byref(stats))
         _check(st)
         return (b, s2, v, status), stats
 
