@@ -1,8 +1,9 @@
 // FP64 product C = alpha op(A) B + beta Cin for the per-block solve
 // X~ = L^-1 X and the refinement residual X - L X~ (also the setup's panel and
 // trailing products and the adjoint's L-bar update): A column-major and lower
-// triangular (or full), B column-major, C column-major, optionally only the
-// tiles that reach C's lower part.  The same
+// or upper triangular (or full), B column-major (full, or lower triangular
+// under a full A), C column-major, optionally only the tiles that reach C's
+// lower part.  The same
 // v_mfma_f64_4x4x4_4b_f64 accumulation as gemm_f64_kernel with the k order
 // permuted within each 16-deep stage; operands reach LDS by direct
 // global-to-LDS loads into a ring of stages.
@@ -51,11 +52,13 @@ void trmm_f64_dma_kernel(GemmArgs g) {
   const int i0 = ti * BM, j0 = tj * BN;
   if (g.c_lower && (i0 + BM - 1) < (j0 + g.c_diag)) return;   // a tile wholly above the lower part
   // k range of the tile: a lower-triangular A ends at the tile's last row, an upper-triangular one starts at its
-  // first (both hold explicit zeros across the diagonal block)
+  // first, a lower-triangular B starts at the tile's first column (each holds explicit zeros across its diagonal
+  // block)
   int khi = g.K;
   if (g.a_tri == TRI_LOWER) khi = imin(khi, i0 + BM);
   const int nk = (khi + BK - 1) / BK;
-  const int k0 = (g.a_tri == TRI_UPPER) ? i0 / BK : 0;
+  int k0 = (g.a_tri == TRI_UPPER) ? i0 / BK : 0;
+  if (g.b_tri == TRI_LOWER) k0 = imax(k0, j0 / BK);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WGM, wn = wave / WGM;
@@ -200,7 +203,8 @@ void trmm_f64_dma_kernel(GemmArgs g) {
 inline bool trmm_dma_ok(const GemmArgs& g) {
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   if (!al16(g.A) || !al16(g.B) || (g.lda & 1) || (g.ldb & 1)) return false;
-  if (g.b_tri != TRI_NONE || g.a_diag != 0) return false;
+  if (g.b_tri == TRI_UPPER || (g.b_tri == TRI_LOWER && (g.b_diag != 0 || g.a_tri != TRI_NONE)) || g.a_diag != 0)
+    return false;
   if (g.M <= 0 || g.K % DB_BK || g.K <= 0 || g.ncols <= 0 || g.mvalid > g.M) return false;
   if (g.lda < (int64_t)(g.M + DB_BM - 1) / DB_BM * DB_BM || g.ldb < g.K) return false;
   if ((15 * g.lda + DB_BM) * 8 >= ((int64_t)1 << 32) || (63 * g.ldb + DB_BK) * 8 >= ((int64_t)1 << 32)) return false;

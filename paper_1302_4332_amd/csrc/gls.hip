@@ -88,7 +88,7 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   if (n > (int64_t)1 << 20) return false;
   const int64_t N = padded_n(n);
   const int64_t bc = o->block_cols;
-  const int Kt = (int)(N / NB_LEAF);
+  const int Kt = (int)((n + NB_LEAF - 1) / NB_LEAF);   // rows past n are the identity: factored only up to a leaf
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t at = off;
@@ -99,6 +99,7 @@ bool plan_workspace(int64_t n, int32_t p, const gls_opts* o, Plan* pl) {
   pl->p = p;
   pl->N = N;
   pl->bc = bc;
+  pl->leaves = Kt;
   pl->off_info = take(256);
   pl->off_small = take(sizeof(double) * 2048);
   pl->off_gram = take(sizeof(double) * PMAX * PMAX);
@@ -259,7 +260,7 @@ static int grid_for(int64_t total) {
 // compute units that L22's latency-bound small steps leave idle.  Each depth
 // has its own T region and join event.
 struct SetupSide {
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;   // the caller's side stream (nullptr: none)
   hipEvent_t fork = nullptr;
   hipEvent_t join[16] = {};
   double* base = nullptr;   // side scratch (plan offsets side_at[depth])
@@ -272,12 +273,11 @@ struct SetupSide {
     for (hipEvent_t e : join)
       if (e) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
-    if (st) (void)hipStreamDestroy(st);
   }
-  hipError_t init(double* scratch) {
+  hipError_t init(hipStream_t side, double* scratch) {
+    st = side;
     base = scratch;
-    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
     for (int d = 0; d < 16 && e == hipSuccess; ++d) e = hipEventCreateWithFlags(&join[d], hipEventDisableTiming);
     return e;
   }
@@ -521,14 +521,14 @@ static gls_status setup_args(const char* fn, int64_t n, int32_t p, const double*
 }
 
 // The study setup (Sec. 2.1, Listing 1 before the SNP loop) into a fresh
-// handle c whose regions lie in the workspace ws (plan pl).  With side_stream
-// the products T = L21 L11^-1 of big recursion nodes overlap on a side stream;
-// without it every kernel runs on s (the same kernels in the same order per
-// output, so the same results).  Synchronizes s: on return nothing enqueued
-// here still runs.
+// handle c whose regions lie in the workspace ws (plan pl).  With a side
+// stream the factorization's off-path products overlap there (chol_inv_rec);
+// without one every kernel runs on s (the same kernels in the same order per
+// output, so the same results).  Synchronizes s, into which the side stream is
+// joined: on return nothing enqueued here still runs.
 static gls_status setup_into(Ctx* c, const Plan& pl, int64_t n, int32_t p, const double* Phi, int64_t ld_phi,
                              double h2, const double* XL, int64_t ld_xl, const double* y, char* ws,
-                             const gls_opts* opts, bool side_stream, hipStream_t s, int64_t* info) {
+                             const gls_opts* opts, hipStream_t side_st, hipStream_t s, int64_t* info) {
   c->plan = pl;
   c->opts = *opts;
   c->n = n;
@@ -560,12 +560,14 @@ static gls_status setup_into(Ctx* c, const Plan& pl, int64_t n, int32_t p, const
   // info[0]: failing pivot of M, info[1]: failing pivot of S_TL
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<double*>(c->info), (int64_t)4, 0.0);
   hipLaunchKernelGGL(form_m_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->L, (int)N, (int)n, Phi, ld_phi, h2);
-  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Linv, N * N, 0.0);
+  // L^-1 = 0 but for the identity on rows past the factored leaves
+  hipLaunchKernelGGL(identity_tail_kernel, dim3(grid_for(N * N)), dim3(256), 0, s, c->Linv, (int)N,
+                     pl.leaves * NB_LEAF);
   {
     SetupSide side;
-    if (side_stream && (e = side.init(reinterpret_cast<double*>(ws + pl.off_side))) != hipSuccess)
-      return fail(hip_fail(e, "gls_setup: side stream"));
-    chol_inv_rec(c, 0, (int)(N / NB_LEAF), 0, &side, s);
+    if (side_st && (e = side.init(side_st, reinterpret_cast<double*>(ws + pl.off_side))) != hipSuccess)
+      return fail(hip_fail(e, "gls_setup: side stream events"));
+    chol_inv_rec(c, 0, pl.leaves, 0, &side, s);
     // every side product is joined into s by its node's last product
     if (side.err != hipSuccess) return fail(hip_fail(side.err, "gls_setup: side stream fork/join"));
   }
@@ -673,12 +675,6 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
   }
   Ctx* c = new (std::nothrow) Ctx();
   if (!c) return arg_fail("gls_setup: out of host memory");
-  st = setup_into(c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, static_cast<char*>(workspace), opts, true,
-                  static_cast<hipStream_t>(stream), info);
-  if (st != GLS_OK) {
-    delete c;
-    return st;
-  }
   hipError_t e;
   for (int i = 0; i < 2; ++i) {
     if ((e = hipEventCreateWithFlags(&c->ev_copy[i], hipEventDisableTiming)) != hipSuccess ||
@@ -694,6 +690,18 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
       (e = hipStreamCreateWithFlags(&c->own_st[1], hipStreamNonBlocking)) != hipSuccess) {
     gls_destroy(c);
     return hip_fail(e, "gls_setup: stream create");
+  }
+  // the factorization's main and side streams are the pair, after the caller's work
+  if ((e = hipEventRecord(c->ev_join, static_cast<hipStream_t>(stream))) != hipSuccess ||
+      (e = hipStreamWaitEvent(c->own_st[0], c->ev_join, 0)) != hipSuccess) {
+    gls_destroy(c);
+    return hip_fail(e, "gls_setup: stream order");
+  }
+  st = setup_into(c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, static_cast<char*>(workspace), opts, c->own_st[1],
+                  c->own_st[0], info);
+  if (st != GLS_OK) {
+    gls_destroy(c);
+    return st;
   }
   c->ready = true;
   *out = c;
@@ -834,7 +842,7 @@ gls_status gls_solve_noalloc(int64_t n, int32_t p, const double* Phi, int64_t ld
   if ((st = noalloc_workspace(&ws)) != GLS_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ctx c;   // the handle lives in this frame: no heap, no events, no side stream
-  if ((st = setup_into(&c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, ws, opts, false, s, info)) != GLS_OK) return st;
+  if ((st = setup_into(&c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, ws, opts, nullptr, s, info)) != GLS_OK) return st;
   c.ready = true;
   for (int64_t j0 = 0; j0 < m && st == GLS_OK; j0 += c.bc) {
     const int mb = (int)std::min<int64_t>(c.bc, m - j0);

@@ -34,6 +34,7 @@ struct Plan {
   // one region per recursion depth (offsets in doubles from off_side)
   size_t off_side = 0;
   int64_t side_at[16] = {0};
+  int leaves = 0;   // NB_LEAF-row diagonal blocks factored: rows n..N-1 past them are the identity
   size_t total = 0;
 };
 

@@ -29,6 +29,16 @@ __global__ void form_m_kernel(double* __restrict__ L, int N, int n,
   }
 }
 
+// N x N zeros with ones on the diagonal from row r0 on.
+__global__ void identity_tail_kernel(double* __restrict__ p, int N, int r0) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)N * N;
+  for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % N), j = (int)(idx / N);
+    p[idx] = (i == j && i >= r0) ? 1.0 : 0.0;
+  }
+}
+
 __global__ void fill_kernel(double* __restrict__ p, int64_t count, double v) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; idx < count; idx += (int64_t)gridDim.x * blockDim.x) p[idx] = v;
