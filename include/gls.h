@@ -29,10 +29,14 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *   - The caller owns every input, output and the workspace.  The library
  *     never allocates device memory.  Host-side resources: the small handle
- *     and its HIP events (freed by gls_destroy); gls_setup also creates a
- *     side stream and events of its own, which it synchronizes and destroys
- *     before returning; gls_stream_file runs a reader thread that is joined
- *     before the call returns.
+ *     with its HIP events and two streams of its own for streamed studies
+ *     (see gls_stream), freed by gls_destroy; gls_setup also creates a side
+ *     stream and events of its own, which it synchronizes and destroys before
+ *     returning; gls_stream_file runs a reader thread that is joined before
+ *     the call returns.
+ *     gls_setup also creates events of its own, which it destroys before
+ *     returning; gls_stream_file runs a reader thread that is joined before
+ *     the call returns.
  *   - Work the library enqueues on a caller's stream reads and writes the
  *     workspace asynchronously: the workspace must not be freed or reused
  *     until that stream has finished it.
@@ -172,11 +176,14 @@ typedef struct {
  * (block_cols / 8, growing by a quarter per block, multiples of 64), so the
  * first copy, which nothing overlaps, is short; results are bitwise the same
  * for any blocking.
- * copy_stream NULL (recommended): the handle's own compute and copy streams,
- * created one after the other at setup so that they sit on different hardware
- * queues, run the study after the work already queued on compute_stream.  A
- * caller-given copy stream that shares compute_stream's hardware queue (HIP
- * multiplexes streams over a few queues) serializes every copy with the solves.
+ * copy_stream NULL (recommended): the study runs on the handle's own compute
+ * and copy streams, after the work already queued on compute_stream.  HIP
+ * multiplexes streams onto a few hardware queues, and on a shared queue the
+ * copy pipeline's cross-stream waits hold up the other stream: copies and
+ * solves would run one after another.  gls_setup therefore checks that a wait
+ * on its copy stream does not hold up its compute stream, and re-creates the
+ * copy stream (at most four times) until it does not.  A caller-given copy
+ * stream gets no such check.
  * Returns after every result has landed.  col0 > 0 resumes an interrupted
  * run: outputs for columns < col0 are not touched.  col0 == m (an empty
  * stream) returns GLS_OK at once, and the pointers may then be NULL. */

@@ -631,6 +631,52 @@ static gls_status setup_into(Ctx* c, const Plan& pl, int64_t n, int32_t p, const
   return GLS_OK;
 }
 
+// The handle's compute and copy streams.  HIP multiplexes a process's plain
+// streams onto a few hardware queues.  On a shared queue a cross-stream wait
+// holds up the other stream's work queued behind it, so the copy pipeline
+// (copies wait for the solve that last read their buffer, solves for their
+// copy) would run copies and solves one after another.  The check: `c` idles
+// about 0.4 ms in bounded sleeps, `copy` waits for it, and an empty kernel on
+// `comp` must finish while c still runs.  (Kernels of different streams on one
+// queue do overlap, so sharing c's queue does not fail the check; a slow host
+// can only make its answer a false "shared".)  The copy stream is re-created
+// until the check passes, at most four times.
+__global__ void idle_kernel(int rounds) {
+  for (int r = 0; r < rounds; ++r) __builtin_amdgcn_s_sleep(127);
+}
+__global__ void empty_kernel() {}
+
+static bool wait_is_isolated(hipStream_t comp, hipStream_t copy, hipStream_t c, hipEvent_t ev) {
+  hipLaunchKernelGGL(idle_kernel, dim3(1), dim3(64), 0, c, 100);
+  bool ok = hipEventRecord(ev, c) == hipSuccess && hipStreamWaitEvent(copy, ev, 0) == hipSuccess;
+  hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, copy);
+  hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, comp);
+  ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(comp) == hipSuccess;
+  ok = ok && hipEventQuery(ev) == hipErrorNotReady;
+  (void)hipStreamSynchronize(c);
+  (void)hipStreamSynchronize(copy);
+  (void)hipGetLastError();
+  return ok;
+}
+
+static hipError_t make_stream_pair(hipStream_t st[2], hipStream_t caller, hipEvent_t ev) {
+  hipError_t e = hipStreamCreateWithFlags(&st[0], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&st[1], hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  std::vector<hipStream_t> rejected;
+  for (int tries = 0; tries < 4 && !wait_is_isolated(st[0], st[1], caller, ev); ++tries) {
+    hipStream_t fresh = nullptr;
+    if (hipStreamCreateWithFlags(&fresh, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      break;
+    }
+    rejected.push_back(st[1]);   // kept until the search ends, so its queue is not handed out again
+    st[1] = fresh;
+  }
+  for (hipStream_t r : rejected) (void)hipStreamDestroy(r);
+  return hipSuccess;
+}
+
 }  // namespace gls
 
 extern "C" {
@@ -683,25 +729,25 @@ gls_status gls_setup(gls_handle* out, int64_t n, int32_t p, const double* Phi, i
       return hip_fail(e, "gls_setup: event create");
     }
   }
-  // created one right after the other: the runtime gives a new stream its least
-  // used hardware queue, so the pair does not share one
-  if ((e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&c->own_st[0], hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&c->own_st[1], hipStreamNonBlocking)) != hipSuccess) {
+  if ((e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess) {
     gls_destroy(c);
-    return hip_fail(e, "gls_setup: stream create");
+    return hip_fail(e, "gls_setup: event create");
   }
-  // the factorization's main and side streams are the pair, after the caller's work
-  if ((e = hipEventRecord(c->ev_join, static_cast<hipStream_t>(stream))) != hipSuccess ||
-      (e = hipStreamWaitEvent(c->own_st[0], c->ev_join, 0)) != hipSuccess) {
+  hipStream_t side = nullptr;   // the factorization's side products
+  if ((e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking)) != hipSuccess) {
     gls_destroy(c);
-    return hip_fail(e, "gls_setup: stream order");
+    return hip_fail(e, "gls_setup: side stream create");
   }
-  st = setup_into(c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, static_cast<char*>(workspace), opts, c->own_st[1],
-                  c->own_st[0], info);
+  st = setup_into(c, pl, n, p, Phi, ld_phi, h2, XL, ld_xl, y, static_cast<char*>(workspace), opts, side,
+                  static_cast<hipStream_t>(stream), info);
+  (void)hipStreamDestroy(side);   // joined into `stream`, which setup_into synchronized
   if (st != GLS_OK) {
     gls_destroy(c);
     return st;
+  }
+  if ((e = make_stream_pair(c->own_st, static_cast<hipStream_t>(stream), c->ev_join)) != hipSuccess) {
+    gls_destroy(c);
+    return hip_fail(e, "gls_setup: stream create");
   }
   c->ready = true;
   *out = c;

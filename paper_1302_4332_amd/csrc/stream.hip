@@ -98,18 +98,18 @@ std::vector<int64_t> block_schedule(int64_t bc, int64_t total) {
   return bstart;
 }
 
-// The streams a study runs on.  A caller that passes a copy stream gets its own
-// pair; otherwise the handle's pair runs it, after the work already queued on
-// the caller's compute stream.
+// The streams a study runs on: the caller's pair, or, without a copy stream,
+// the handle's own pair (checked at setup not to share a hardware queue),
+// after the work already queued on the caller's compute stream.
 struct RunStreams {
   hipStream_t sc = nullptr, sx = nullptr;
 };
 
 hipError_t run_streams(Ctx* c, void* compute_stream, void* copy_stream, RunStreams* r) {
   const hipStream_t caller = static_cast<hipStream_t>(compute_stream);
-  if (copy_stream) {
+  if (copy_stream || (c->opts.flags & GLS_STREAM_SERIAL)) {   // serial: every copy on the compute stream
     r->sc = caller;
-    r->sx = static_cast<hipStream_t>(copy_stream);
+    r->sx = copy_stream ? static_cast<hipStream_t>(copy_stream) : caller;
     return hipSuccess;
   }
   r->sc = c->own_st[0];
@@ -124,7 +124,7 @@ hipError_t run_streams(Ctx* c, void* compute_stream, void* copy_stream, RunStrea
 
 template <typename T>
 static gls_status stream_run(gls_handle h, int64_t m, int64_t col0, const T* XR_host, int64_t ld_xr, double* b_host,
-                             double* sigma2_host, double* v_host, int32_t* status_host, RunStreams rs,
+                             double* sigma2_host, double* v_host, int32_t* status_host, const RunStreams& rs,
                              gls_stream_stats* stats_out) {
   Ctx* c = h;
   if (m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream: need 0 <= col0 <= m");
