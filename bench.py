@@ -82,9 +82,27 @@ def blas_threads() -> int:
         return os.cpu_count() or 1
 
 
+def timed_runs(fn, reps):
+    """Time fn() reps times (each bracketed by device synchronizations);
+    returns (median ms, every run's ms, the value fn returned on the median run)."""
+    import torch
+
+    runs = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        runs.append(((time.perf_counter() - t0) * 1e3, out))
+    order = sorted(range(reps), key=lambda i: runs[i][0])
+    med = runs[order[reps // 2]]
+    return med[0], [r[0] for r in runs], med[1]
+
+
 def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
     """Mixed-precision forms on the same workload, and the adjoint on the
-    n = 4,096 differentiation study; one timed study each."""
+    n = 4,096 differentiation study; the median of args.sub_reps timed studies
+    each (after one untimed)."""
     import torch
 
     from oracle import gls_oracle as O
@@ -134,11 +152,7 @@ def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
             return ph
 
         study(False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ph = study(True)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
+        ms, runs, ph = timed_runs(lambda: study(True), args.sub_reps)
         g = b_d.cpu().numpy()[samp]
         ok = ref["status"] == 0
         err = np.max(np.abs(g[ok] - ref["b"][ok]), axis=1) / np.max(np.abs(ref["b"][ok]), axis=1)
@@ -149,7 +163,7 @@ def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
             "snps_per_s": m / (ms / 1e3), "ms_per_study": ms, "max_rel_err_b_sampled": float(err.max()),
             "lowp_tflops": lp_flops / (lp_ms / 1e3) / 1e12, "lowp_peak": PEAK_TFLOPS[prec],
             "fp64_residual_tflops": (r_flops / (res_ms / 1e3) / 1e12) if res_ms else None,
-            "phases_ms": {k: v[1] for k, v in ph.items()}}
+            "phases_ms": {k: v[1] for k, v in ph.items()}, "runs_ms": runs}
         log(f"{prec} x{sweeps}: {m / (ms / 1e3):,.0f} SNPs/s, max rel err {err.max():.2e}")
         del b_d, s2_d, v_d, st_d
     # adjoint on the differentiation study
@@ -166,13 +180,9 @@ def measure_forms(args, st, Phi_d, XL_d, y_d, X_d, m, dev):
             t2_loss(b, s2, v).backward()
             return h2t.grad
         fwd_bwd()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        gh = fwd_bwd()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
+        ms, runs, gh = timed_runs(fwd_bwd, args.sub_reps)
         res[f"adjoint_c3_{prec}"] = {"workload": w3.name, "ms_fwd_bwd": ms, "snps_per_s": w3.m / (ms / 1e3),
-                                     "h2_grad": float(gh)}
+                                     "h2_grad": float(gh), "runs_ms": runs}
         log(f"adjoint {prec}: {ms:.1f} ms forward+backward")
     return res
 
@@ -209,11 +219,7 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
         return ctx.profile_read() if profile else None
 
     study(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ph = study(True)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
+    ms, runs, ph = timed_runs(lambda: study(True), args.sub_reps)
     ctx.close()
     g = b_d.cpu().numpy()
     ref = b_fp64_host.numpy()
@@ -224,7 +230,7 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
         "snps_per_s": m / (ms / 1e3), "ms_per_study": ms, "slices": 8,
         "product_ms": wms, "product_fp64_equiv_tflops": float(n) * n * m / (wms / 1e3) / 1e12,
         "int8_tops": 8.0 * n * n * m / (wms / 1e3) / 1e12, "int8_peak_tops": 5000.0,
-        "max_rel_diff_vs_fp64_path": float(rel.max()),
+        "max_rel_diff_vs_fp64_path": float(rel.max()), "runs_ms": runs,
         "note": "same study, SNPs as bytes; product from exact int8 slice products (FP64-level accuracy)"}
     log(f"int8 emulation: {m / (ms / 1e3):,.0f} SNPs/s, product {wms:.1f} ms, max rel diff vs FP64 path {rel.max():.2e}")
     del b_d, s2_d, v_d, st_d
@@ -237,10 +243,12 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
         for prec in ("fp64", "int8_emu"):
             ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec)
             ctx.stream(H, packed=packed)
-            (_, _, _, _), ss = ctx.stream(H, packed=packed)
+            stats = sorted((ctx.stream(H, packed=packed)[1] for _ in range(args.sub_reps)), key=lambda x: x.wall_ms)
+            ss = stats[len(stats) // 2]
             res[f"stream_{fmt}_{prec}"] = {"snps_per_s": m / (ss.wall_ms / 1e3), "wall_ms": ss.wall_ms,
                                            "compute_ms": ss.compute_ms,
-                                           "h2d_GBps": ss.h2d_bytes / (ss.wall_ms / 1e3) / 1e9}
+                                           "h2d_GBps": ss.h2d_bytes / (ss.wall_ms / 1e3) / 1e9,
+                                           "runs_wall_ms": [x.wall_ms for x in stats]}
             log(f"stream {fmt} {prec}: {m / (ss.wall_ms / 1e3):,.0f} SNPs/s")
             ctx.close()
     # from storage: the dosages written to a file, then streamed through the
@@ -251,15 +259,20 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
             H.numpy().tofile(path)
             for prec in ("fp64", "int8_emu"):
                 ctx = GLSContext(Phi_d, h2, XL_d, y_d, block_cols=bc, precision=prec)
-                fd = os.open(path, os.O_RDONLY)
-                os.fsync(fd)
-                os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
-                os.close(fd)
-                (_, _, _, _), fs = ctx.stream_file(path, m, torch.uint8 if fmt == "u8" else "u2")
+                stats = []
+                for _ in range(args.sub_reps):
+                    fd = os.open(path, os.O_RDONLY)
+                    os.fsync(fd)
+                    os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+                    os.close(fd)
+                    stats.append(ctx.stream_file(path, m, torch.uint8 if fmt == "u8" else "u2")[1])
+                stats.sort(key=lambda x: x.wall_ms)
+                fs = stats[len(stats) // 2]
                 res[f"stream_file_{fmt}_{prec}"] = {
                     "snps_per_s": m / (fs.wall_ms / 1e3), "wall_ms": fs.wall_ms, "read_ms": fs.read_ms,
                     "file_GBps": fs.file_bytes / (fs.read_ms / 1e3) / 1e9 if fs.read_ms else None,
-                    "compute_ms": fs.compute_ms, "note": "page cache of the file dropped before the run"}
+                    "compute_ms": fs.compute_ms, "runs_wall_ms": [x.wall_ms for x in stats],
+                    "note": "page cache of the file dropped before each run"}
                 log(f"stream file {fmt} {prec}: {m / (fs.wall_ms / 1e3):,.0f} SNPs/s (read {fs.read_ms:.0f} ms)")
                 ctx.close()
     del G_h, G2_h
@@ -424,6 +437,8 @@ def main():
     ap.add_argument("--no-serial", action="store_true", help="skip the no-overlap ablation")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision and adjoint measurements")
     ap.add_argument("--no-bytes", action="store_true", help="skip the genotype-byte and packed-dosage measurements")
+    ap.add_argument("--sub-reps", type=int, default=3,
+                    help="timed runs of each forms / bytes / adjoint measurement (the median is reported)")
     ap.add_argument("--scale", default=None,
                     help="also stream a whole large workload (e.g. c2_n10k_m1M) from a cycled pinned pool")
     ap.add_argument("--calib-copy", action="store_true",
