@@ -336,7 +336,11 @@ class GLSContext:
         or uint8 genotype bytes, or with packed=True (m, ceil(n / 4)) uint8
         packed 2-bit dosages.
 
-        Returns (b, sigma2, v, status) host tensors and the stats struct.
+        The study runs after the work queued on compute_stream (default: the
+        current stream).  With copy_stream None it runs on the handle's own
+        compute and copy streams, which setup checked do not share a hardware
+        queue; a caller-given copy stream gets no such check.  Returns
+        (b, sigma2, v, status) host tensors and the stats struct.
         """
         _need(XR_host, "XR_host", XR_host.dtype if XR_host.dtype in (torch.uint8, torch.float64) else torch.float64,
               cuda=False)
