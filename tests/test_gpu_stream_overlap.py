@@ -44,3 +44,21 @@ def test_every_pass_overlaps_copies_and_solves():
                 assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
     for ctx in ctxs:
         ctx.close()
+
+
+def test_caller_streams_give_the_same_outputs():
+    """A caller-given copy stream (and compute stream) runs the same kernels on
+    the caller's streams: bitwise the outputs of the handle's own pair."""
+    m = 3000
+    st = synth.make_study("c0_small", m=m)
+    Phi, XL, y = (torch.tensor(np.ascontiguousarray(a), device=DEV) for a in (st.Phi, st.XL, st.y))
+    host = torch.from_numpy(st.snps(0, m)).pin_memory()
+    ctx = GLSContext(Phi, st.w.h2, XL, y, block_cols=512)
+    ref, _ = ctx.stream(host)
+    cs, xs = torch.cuda.Stream(), torch.cuda.Stream()
+    for kw in ({"copy_stream": xs}, {"compute_stream": cs, "copy_stream": xs}):
+        got, stats = ctx.stream(host, **kw)
+        assert stats.blocks == 6
+        for a, b in zip(got, ref):
+            assert np.array_equal(a.numpy().view(np.uint8), b.numpy().view(np.uint8))
+    ctx.close()
