@@ -281,9 +281,10 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
 
 def measure_scale(args, dev):
     """Streamed rate over a whole large study (m = 1,000,000 or 2,000,000): a
-    pinned pool of distinct SNP blocks (about 21 GB) is streamed once untimed,
-    then again and again until the study's m SNPs have gone through; the work
-    per SNP is the same as for m distinct SNPs.  Setup excluded."""
+    pinned pool of distinct SNP blocks (about 21 GB) is streamed untimed until
+    two passes agree, then again and again until the study's m SNPs have gone
+    through; the work per SNP is the same as for m distinct SNPs.  Setup
+    excluded."""
     import torch
 
     from paper_1302_4332_amd import synth
@@ -303,9 +304,14 @@ def measure_scale(args, dev):
     ctx = GLSContext(Phi_d, w.h2, XL_d, y_d, block_cols=bc)
     out = (torch.empty((pool, p), dtype=torch.float64).pin_memory(), torch.empty(pool, dtype=torch.float64).pin_memory(),
            torch.empty(pool, dtype=torch.float64).pin_memory(), torch.empty(pool, dtype=torch.int32).pin_memory())
-    # warm-up: the whole pool once (the first pass over freshly written pinned memory ran its solves up to 30%
-    # slower on some boxes)
-    ctx.stream(host, out=out)
+    # warm-up: whole passes over the pool until two in a row agree within 3% in solve time (at most four; after
+    # the host-side fill the first passes of a run solved 15-30% slower on some boxes)
+    prev = None
+    for _ in range(4):
+        cms = ctx.stream(host, out=out)[1].compute_ms
+        if prev is not None and abs(cms - prev) <= 0.03 * prev:
+            break
+        prev = cms
     torch.cuda.synchronize()
     done, wall_ms, compute_ms, passes = 0, 0.0, 0.0, 0
     pass_ms = []   # (device wall, summed solve time) per pass: the copies hide under the solves when they agree
