@@ -6,6 +6,8 @@
   has rank 2,000 plus its 1e-3 ridge, so at h2 = 1 the condition number of M
   is about 4e3 (about 65 for L): the explicit-inverse product and the
   low-precision refinement are least safe here.
+- The int8-slice product on genotype bytes at the same three h2 values, to
+  the plain-FP64 bar.
 - Non-integer SNP values (imputed-style dosages x + U(-0.5, 0.5), and
   standardized genotypes): the FP16/BF16 first solve is no longer exact on them.
 
@@ -97,6 +99,28 @@ def test_h2_edges_refined(kin2304, h2, precision):
     k = EDGE_SWEEPS[h2][precision]
     g = _run(Phi, h2, XL, y, XR, 128, precision, k)
     compare(g, r, 1e-8)
+
+
+@pytest.mark.parametrize("h2", [0.0, 0.95, 1.0])
+def test_h2_edges_int8_slices(kin2304, h2):
+    """The int8-slice product at the ends of h2: only the slicing of L^-1 (below
+    2^-56 of each row's largest entry) differs from FP64, so the plain-FP64 bar
+    holds, and at h2 = 0 (L^-1 = I, one nonzero slice per row) the results are
+    the ordinary least-squares ones."""
+    Phi, XL, y, XR = kin2304
+    r = O.gls_sequence(Phi, h2, XL, y, XR)
+    G = torch.tensor(XR.astype(np.uint8), device=DEV)
+    ctx = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=128, precision="int8_emu")
+    outs = [ctx.block_u8(G[j:j + 128]) for j in range(0, G.shape[0], 128)]
+    torch.cuda.synchronize()
+    ctx.close()
+    g = {k: torch.cat([o[i] for o in outs]).cpu().numpy() for i, k in enumerate(["b", "sigma2", "v", "status"])}
+    err = compare(g, r, 1e-10)
+    print(f"h2={h2} int8 slices: max rel err b {err:.1e}")
+    if h2 == 0.0:
+        for i in (0, 137, 299):
+            ols = np.linalg.lstsq(np.c_[XL, XR[i]], y, rcond=None)[0]
+            assert np.max(np.abs(g["b"][i] - ols)) <= 1e-10 * np.max(np.abs(ols))
 
 
 # sweeps after which each refined form meets 1e-8 on non-integer SNP values
