@@ -247,6 +247,33 @@ gls_status gls_backward_block(gls_handle h, int32_t mb, const double* XR, int64_
  * Asynchronous on `stream`. */
 gls_status gls_backward_finish(gls_handle h, double* y_grad, double* h2_grad, void* stream);
 
+/* Adjoint of a streamed study (the buffering of Sec. 3.1 applied to the
+ * adjoint of the per-SNP solve of Sec. 2.1; requires GLS_KEEP_FOR_GRAD).
+ * For SNPs [col0, m) of XR_host (n x m FP64, ld_xr >= n, page-locked host
+ * memory, the layout of gls_stream) runs gls_backward_block on each block in
+ * gls_stream's block schedule: block b+1 is copied into one of two device
+ * buffers on the copy stream while block b's adjoint (which recomputes
+ * X~_R,b from its copy) runs on the compute stream.  b_bar_host (p x m,
+ * ld p), sigma2_bar_host and v_bar_host (m) are the cotangents of the
+ * study's outputs, in host memory; each block's are copied up on the compute
+ * stream just before its adjoint.  If XR_grad_host is not NULL it receives
+ * dL/dX_R (n x m, ld_xr) in host memory, each block's copied down on the
+ * compute stream right after its adjoint (that copy is not overlapped).
+ * The handle's adjoint accumulators add up over calls (col0 > 0 resumes; a
+ * study may also be passed several times); gls_backward_finish then gives
+ * the y and h2 gradients.  With every block but the last a multiple of 16
+ * SNPs wide, the gradients are bitwise those of gls_backward_block over
+ * blocks of any such width.  Streams as for gls_stream.  Returns after every
+ * copy has landed; col0 == m returns GLS_OK at once.  Errors: GLS_ERR_STATE
+ * without GLS_KEEP_FOR_GRAD; GLS_ERR_ARG for col0 outside [0, m], a NULL SNP
+ * matrix or cotangent, or ld_xr < n. */
+gls_status gls_stream_backward(gls_handle h, int64_t m, int64_t col0,
+                               const double* XR_host, int64_t ld_xr,
+                               const double* b_bar_host, const double* sigma2_bar_host,
+                               const double* v_bar_host, double* XR_grad_host,
+                               void* compute_stream, void* copy_stream,
+                               gls_stream_stats* stats_out);
+
 /* Per-phase device time of the block path, measured with HIP events recorded
  * around each phase's kernels on the caller's stream while profiling is on.
  *   phase 0: triangular product X~_R,b = L^-1 X_R,b (plain, or the

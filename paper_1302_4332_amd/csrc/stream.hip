@@ -265,6 +265,124 @@ extern "C" gls_status gls_stream_u2(gls_handle h, int64_t m, int64_t col0, const
 }
 
 // ---------------------------------------------------------------------------
+// gls_stream_backward: the adjoint of a streamed study.  The SNP blocks take
+// the forward stream's route (two device buffers, the next block copied on
+// the copy stream while the current one is worked on), and each block's
+// cotangents go up on the compute stream just before its adjoint, which
+// recomputes the whitened block from the copy it has just received.
+
+static gls_status stream_backward_run(Ctx* c, int64_t m, int64_t col0, const double* XR_host, int64_t ld_xr,
+                                      const double* bbar_host, const double* s2bar_host, const double* vbar_host,
+                                      double* XR_grad_host, const RunStreams& rs, gls_stream_stats* stats_out) {
+  const int64_t rows = c->n;
+  const hipStream_t sc = rs.sc;
+  const hipStream_t sx = (c->opts.flags & GLS_STREAM_SERIAL) ? sc : rs.sx;
+  const int p = c->p;
+  const std::vector<int64_t> bstart = block_schedule(c->bc, m - col0);
+  const int64_t nblk = (int64_t)bstart.size() - 1;
+  gls_stream_stats st{};
+  EventPool pool;
+  hipError_t e;
+  if ((e = pool.make(2 * nblk + 2)) != hipSuccess) return hip_fail(e, "gls_stream_backward: event create");
+  hipEvent_t wall0 = pool.ev[2 * nblk], wall1 = pool.ev[2 * nblk + 1];
+  auto cols_of = [&](int64_t blk) { return bstart[blk + 1] - bstart[blk]; };
+  auto src_of = [&](int64_t blk) { return XR_host + (col0 + bstart[blk]) * ld_xr; };
+  auto copy_x = [&](int64_t blk, int buf, hipStream_t s) -> hipError_t {
+    hipError_t r = h2d_block(c->buf[buf], rows, src_of(blk), ld_xr, cols_of(blk), s);
+    if (r == hipSuccess) r = hipEventRecord(c->ev_copy[buf], s);
+    st.h2d_bytes += (int64_t)sizeof(double) * rows * cols_of(blk);
+    return r;
+  };
+
+  if ((e = hipEventRecord(wall0, sx)) != hipSuccess) return hip_fail(e, "gls_stream_backward: record");
+  if ((e = copy_x(0, 0, sx)) != hipSuccess) return hip_fail(e, "gls_stream_backward: H2D");
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    const int cur = (int)(blk & 1), nxt = cur ^ 1;
+    const int64_t cols = cols_of(blk);
+    const int64_t col = col0 + bstart[blk];
+    if (blk + 1 < nblk && sx != sc) {
+      // the other buffer may only be overwritten once the adjoint that last read it is done
+      if (blk >= 1 && (e = hipStreamWaitEvent(sx, c->ev_comp[nxt], 0)) != hipSuccess)
+        return hip_fail(e, "gls_stream_backward: wait");
+      if ((e = copy_x(blk + 1, nxt, sx)) != hipSuccess) return hip_fail(e, "gls_stream_backward: H2D");
+    }
+    if (sx == sc && blk >= 1 && (e = copy_x(blk, cur, sc)) != hipSuccess)
+      return hip_fail(e, "gls_stream_backward: H2D");
+    // this block's cotangents into the result staging buffers (unused by the adjoint itself)
+    struct {
+      void* dst;
+      const void* src;
+      size_t bytes;
+    } up[3] = {{c->ob, bbar_host + col * p, sizeof(double) * p * cols},
+               {c->os2, s2bar_host + col, sizeof(double) * cols},
+               {c->ov, vbar_host + col, sizeof(double) * cols}};
+    for (int q = 0; q < 3; ++q) {
+      if ((e = hipMemcpyAsync(up[q].dst, up[q].src, up[q].bytes, hipMemcpyHostToDevice, sc)) != hipSuccess)
+        return hip_fail(e, "gls_stream_backward: cotangent H2D");
+      st.h2d_bytes += (int64_t)up[q].bytes;
+    }
+    if ((e = hipStreamWaitEvent(sc, c->ev_copy[cur], 0)) != hipSuccess) return hip_fail(e, "gls_stream_backward: wait");
+    if ((e = hipEventRecord(pool.ev[2 * blk], sc)) != hipSuccess) return hip_fail(e, "gls_stream_backward: record");
+    gls_status r = block_backward(c, (int)cols, c->buf[cur], rows, c->ob, c->os2, c->ov, nullptr, sc);
+    if (r != GLS_OK) return r;
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "gls_stream_backward: launch");
+    if ((e = hipEventRecord(c->ev_comp[cur], sc)) != hipSuccess) return hip_fail(e, "gls_stream_backward: record");
+    if ((e = hipEventRecord(pool.ev[2 * blk + 1], sc)) != hipSuccess) return hip_fail(e, "gls_stream_backward: record");
+    if (XR_grad_host) {
+      // X_R bar of the block stays in Xb (ld N) until the next block's adjoint; copied out before it on the same
+      // stream
+      if ((e = hipMemcpy2DAsync(XR_grad_host + col * ld_xr, sizeof(double) * ld_xr, c->Xb, sizeof(double) * c->N,
+                                sizeof(double) * rows, cols, hipMemcpyDeviceToHost, sc)) != hipSuccess)
+        return hip_fail(e, "gls_stream_backward: D2H of the X_R gradient");
+      st.d2h_bytes += (int64_t)sizeof(double) * rows * cols;
+    }
+  }
+  if ((e = hipEventRecord(wall1, sc)) != hipSuccess) return hip_fail(e, "gls_stream_backward: record");
+  if ((e = hipStreamSynchronize(sc)) != hipSuccess) return hip_fail(e, "gls_stream_backward: synchronize");
+  if ((e = hipStreamSynchronize(sx)) != hipSuccess) return hip_fail(e, "gls_stream_backward: synchronize");
+  float ms = 0.f;
+  if ((e = hipEventElapsedTime(&ms, wall0, wall1)) != hipSuccess) return hip_fail(e, "gls_stream_backward: elapsed");
+  st.wall_ms = ms;
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    float t = 0.f;
+    if ((e = hipEventElapsedTime(&t, pool.ev[2 * blk], pool.ev[2 * blk + 1])) != hipSuccess)
+      return hip_fail(e, "gls_stream_backward: elapsed");
+    st.compute_ms += t;
+  }
+  st.blocks = nblk;
+  if (stats_out) *stats_out = st;
+  return GLS_OK;
+}
+
+extern "C" gls_status gls_stream_backward(gls_handle h, int64_t m, int64_t col0, const double* XR_host,
+                                          int64_t ld_xr, const double* b_bar_host, const double* sigma2_bar_host,
+                                          const double* v_bar_host, double* XR_grad_host, void* compute_stream,
+                                          void* copy_stream, gls_stream_stats* stats_out) {
+  Ctx* c = h;
+  if (!c || !c->ready || !c->grad) {
+    set_last_error_str("gls_stream_backward: handle not set up with GLS_KEEP_FOR_GRAD");
+    return GLS_ERR_STATE;
+  }
+  if (m < 0 || col0 < 0 || col0 > m) return arg_fail("gls_stream_backward: need 0 <= col0 <= m");
+  if (col0 == m) {
+    if (stats_out) *stats_out = gls_stream_stats{};
+    return GLS_OK;
+  }
+  if (!XR_host || ld_xr < c->n) return arg_fail("gls_stream_backward: the SNP matrix is NULL or ld_xr < n");
+  if (!b_bar_host || !sigma2_bar_host || !v_bar_host) return arg_fail("gls_stream_backward: NULL cotangent");
+  RunStreams rs;
+  hipError_t e = run_streams(c, compute_stream, copy_stream, &rs);
+  if (e != hipSuccess) return hip_fail(e, "gls_stream_backward: stream order");
+  const gls_status r = stream_backward_run(c, m, col0, XR_host, ld_xr, b_bar_host, sigma2_bar_host, v_bar_host,
+                                           XR_grad_host, rs, stats_out);
+  if (r != GLS_OK) {
+    (void)hipStreamSynchronize(rs.sc);
+    (void)hipStreamSynchronize(rs.sx);
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
 // Streaming from storage: reader thread -> three host buffers -> two device
 // buffers.
 

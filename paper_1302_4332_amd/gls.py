@@ -78,6 +78,8 @@ SIGNATURES = {
                                        _P, _P, _P, _P, _P, _P, ctypes.POINTER(GlsStreamStats)]),
     "gls_backward_block": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _P, _P, _P, _P]),
     "gls_backward_finish": (ctypes.c_int, [_P, _P, _P, _P]),
+    "gls_stream_backward": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
+                                           ctypes.POINTER(GlsStreamStats)]),
     "gls_profile_enable": (ctypes.c_int, [_P, _I32]),
     "gls_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(GlsPhaseStats), _I32]),
     "gls_destroy": (None, [_P]),
@@ -372,6 +374,71 @@ class GLSContext:
                    _ptr(status), self._use(cs), xs, ctypes.byref(stats))
         _check(st)
         return (b, s2, v, status), stats
+
+
+    def stream_backward(self, XR_host, b_bar, sigma2_bar, v_bar, col0: int = 0, XR_grad=None, compute_stream=None,
+                        copy_stream=None):
+        """Adjoint of a streamed study (the handle needs keep_for_grad=True):
+        SNPs [col0, m) of the pinned host tensor XR_host (m, n) float64 with the
+        cotangents b_bar (m, p), sigma2_bar (m,), v_bar (m,) of its outputs
+        (float64 host tensors, page-locked for overlapped copies).  XR_grad,
+        if given, is a host tensor (m, n) that receives d loss / d X_R.  The
+        adjoint sums add up in the handle until backward_finish().  Streams as
+        for stream().  Returns the stats struct."""
+        _need(XR_host, "XR_host", cuda=False)
+        if XR_host.is_cuda:
+            raise TypeError("XR_host must be a host tensor (page-locked: .pin_memory())")
+        if XR_host.dim() != 2 or XR_host.shape[1] != self.n:
+            raise ValueError(f"XR_host must have shape (m, {self.n})")
+        m = XR_host.shape[0]
+        for t, name, shape in ((b_bar, "b_bar", (m, self.p)), (sigma2_bar, "sigma2_bar", (m,)),
+                               (v_bar, "v_bar", (m,))) + (((XR_grad, "XR_grad", (m, self.n)),) if XR_grad is not None
+                                                           else ()):
+            _need(t, name, cuda=False)
+            if t.is_cuda or tuple(t.shape) != shape:
+                raise ValueError(f"{name} must be a host tensor of shape {shape}")
+        stats = GlsStreamStats()
+        cs = compute_stream or torch.cuda.current_stream()
+        xs = self._use(copy_stream) if copy_stream is not None else ctypes.c_void_p(None)
+        st = lib().gls_stream_backward(self.handle, m, col0, _ptr(XR_host), self.n, _ptr(b_bar), _ptr(sigma2_bar),
+                                       _ptr(v_bar), _ptr(XR_grad), self._use(cs), xs, ctypes.byref(stats))
+        _check(st)
+        return stats
+
+    def backward_finish(self, stream=None):
+        """(y_grad (n,), h2_grad (1,)) device tensors from the adjoint sums of the
+        blocks passed since setup or the last finish; resets the sums."""
+        dev = self.workspace.device
+        y_grad = torch.empty(self.n, dtype=torch.float64, device=dev)
+        h2_grad = torch.empty(1, dtype=torch.float64, device=dev)
+        _check(lib().gls_backward_finish(self.handle, _ptr(y_grad), _ptr(h2_grad), self._use(stream)))
+        return y_grad, h2_grad
+
+
+def stream_grad(Phi, h2, XL, y, XR_host, loss, *, block_cols: int, precision="fp64", refine_sweeps: int = 0,
+                XR_grad=None):
+    """d loss / d (y, h2) (and d loss / d X_R into the host tensor XR_grad, if
+    given) for a study whose SNPs (XR_host: pinned (m, n) float64) stay in host
+    memory: the study is streamed forward (gls_stream), loss(b, sigma2, v) is
+    differentiated by torch on the device outputs, and the study is streamed
+    again through the adjoint (gls_stream_backward, then gls_backward_finish).
+    Returns (loss value, y_grad, h2_grad, (b, sigma2, v, status) host tensors)."""
+    g = GLSContext(Phi, h2, XL, y, block_cols=block_cols, precision=precision, refine_sweeps=refine_sweeps,
+                   keep_for_grad=True)
+    try:
+        outs, _ = g.stream(XR_host)
+        dev = Phi.device
+        leaves = [t.to(dev).requires_grad_(True) for t in outs[:3]]
+        value = loss(*leaves)
+        grads = torch.autograd.grad(value, leaves, allow_unused=True)
+        cot = [torch.zeros_like(t) if gr is None else gr for t, gr in zip(leaves, grads)]
+        cot = [c.detach().cpu().pin_memory() for c in cot]
+        g.stream_backward(XR_host, *cot, XR_grad=XR_grad)
+        y_grad, h2_grad = g.backward_finish()
+        torch.cuda.current_stream().synchronize()
+    finally:
+        g.close()
+    return float(value.detach()), y_grad, h2_grad, outs
 
 
 class GLSFunction(torch.autograd.Function):

@@ -1,0 +1,161 @@
+"""The adjoint of a streamed study (GPU, through the C-ABI): gls_stream_backward
+over SNP blocks held in page-locked host memory, then gls_backward_finish.
+
+- Against the FP64 CPU autograd reference of Eq. 1 (loss sum_i t_i^2): every
+  entry of the y and X_R gradients within 1e-8 element-wise (floor one
+  millionth of the largest entry), the h2 gradient relative 1e-8; in FP64 and
+  refined FP32.
+- Bitwise equal to the device-resident adjoint (GLSFunction, gls_backward_block
+  per block), with and without the opening ramp of short blocks (every block
+  but the last a multiple of 16 SNPs), when resumed with col0, in serial mode
+  and on caller-given streams.
+- Arbitrary cotangents of all three outputs against the reference VJP.
+- Error paths: no GLS_KEEP_FOR_GRAD, col0 outside [0, m], a wrong shape.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gls_grad as G
+from paper_1302_4332_amd import synth
+from paper_1302_4332_amd.gls import GLSContext, GLSError, GLSFunction, stream_grad, t2_loss
+from parity_util import elementwise_close
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL_G = 1e-8
+
+
+def _t(a, grad=False):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV, requires_grad=grad)
+
+
+def _problem(n, p, m, seed, h2):
+    Phi = synth.kinship(n, seed)
+    XL = synth.covariates(n, p, seed, "sex_age" if p == 4 else "gauss")
+    y = synth.phenotype(n, seed)
+    XR = synth.genotypes(n, 0, m, seed)
+    return Phi, h2, XL, y, XR
+
+
+def _resident(Phi, h2, XL, y, XR, bc, precision, sweeps):
+    yt, XRt = _t(y, True), _t(XR, True)
+    h2t = torch.tensor(h2, dtype=torch.float64, device=DEV, requires_grad=True)
+    b, s2, v = GLSFunction.apply(yt, XRt, h2t, _t(Phi), _t(XL), bc, precision, sweeps)
+    t2_loss(b, s2, v).backward()
+    return yt.grad.cpu().numpy(), XRt.grad.cpu().numpy(), float(h2t.grad)
+
+
+def _streamed(Phi, h2, XL, y, XR, bc, precision, sweeps):
+    XR_host = torch.tensor(XR).pin_memory()
+    XR_grad = torch.empty_like(XR_host).pin_memory()
+    loss, gy, gh, outs = stream_grad(_t(Phi), h2, _t(XL), _t(y), XR_host, t2_loss, block_cols=bc,
+                                     precision=precision, refine_sweeps=sweeps, XR_grad=XR_grad)
+    return loss, gy.cpu().numpy(), XR_grad.numpy().copy(), float(gh), outs
+
+
+def _cotangents(Phi, h2, XL, y, XR_host, bc, precision, sweeps, **kw):
+    """Outputs of a streamed forward and the t^2 loss's cotangents (pinned)."""
+    g = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=bc, precision=precision, refine_sweeps=sweeps,
+                   keep_for_grad=True, **kw)
+    outs, _ = g.stream(XR_host)
+    leaves = [t.to(DEV).requires_grad_(True) for t in outs[:3]]
+    grads = torch.autograd.grad(t2_loss(*leaves), leaves)
+    return g, [c.detach().cpu().pin_memory() for c in grads]
+
+
+@pytest.mark.parametrize("precision,sweeps", [("fp64", 0), ("fp32_ir", 2)])
+@pytest.mark.parametrize("n,p,m,bc,h2", [(300, 4, 700, 128, 0.3), (257, 3, 333, 100, 0.6)])
+def test_streamed_adjoint_matches_reference(n, p, m, bc, h2, precision, sweeps):
+    Phi, h2, XL, y, XR = _problem(n, p, m, seed=n + m, h2=h2)
+    loss, gy, gX, gh, _ = _streamed(Phi, h2, XL, y, XR, bc, precision, sweeps)
+    rloss, ry, rX, rh = G.loss_and_grads(Phi, h2, XL, y, XR.T)
+    assert loss == pytest.approx(rloss, rel=1e-8)
+    elementwise_close(gy, ry, TOL_G)
+    elementwise_close(gX, rX.T, TOL_G)
+    assert gh == pytest.approx(rh, rel=TOL_G)
+
+
+@pytest.mark.parametrize("precision,sweeps", [("fp64", 0), ("fp32_ir", 2)])
+@pytest.mark.parametrize("n,m,bc", [(300, 700, 128), (330, 5000, 2048)])
+def test_streamed_adjoint_bitwise_equals_resident(n, m, bc, precision, sweeps):
+    """bc = 128: the same blocks as the resident path.  bc = 2,048: the stream
+    opens with blocks of 256, 320, 448, ... (multiples of 64), the resident path
+    runs 2,048, 2,048, 904; the adjoint sums run in SNP order in groups of 16,
+    so the gradients agree bitwise."""
+    Phi, h2, XL, y, XR = _problem(n, 4, m, seed=11, h2=0.4)
+    ry, rX, rh = _resident(Phi, h2, XL, y, XR, bc, precision, sweeps)
+    _, gy, gX, gh, _ = _streamed(Phi, h2, XL, y, XR, bc, precision, sweeps)
+    assert np.array_equal(gy, ry)
+    assert np.array_equal(gX, rX)
+    assert gh == rh
+
+
+def test_resume_serial_and_caller_streams_bitwise():
+    n, m, bc = 300, 3000, 2048
+    Phi, h2, XL, y, XR = _problem(n, 4, m, seed=5, h2=0.45)
+    XR_host = torch.tensor(XR).pin_memory()
+
+    def run(split=None, serial=False, streams=False):
+        g, (bb, sb, vb) = _cotangents(Phi, h2, XL, y, XR_host, bc, "fp64", 0, serial_stream=serial)
+        XR_grad = torch.zeros_like(XR_host).pin_memory()
+        kw = {}
+        if streams:
+            kw = {"compute_stream": torch.cuda.Stream(), "copy_stream": torch.cuda.Stream()}
+        if split is None:
+            s = g.stream_backward(XR_host, bb, sb, vb, XR_grad=XR_grad, **kw)
+            assert s.h2d_bytes == 8 * m * (n + 4 + 2) and s.d2h_bytes == 8 * m * n
+        else:   # the first `split` SNPs, then the rest with col0
+            g.stream_backward(XR_host[:split], bb[:split], sb[:split], vb[:split], XR_grad=XR_grad[:split], **kw)
+            g.stream_backward(XR_host, bb, sb, vb, col0=split, XR_grad=XR_grad, **kw)
+        gy, gh = g.backward_finish()
+        torch.cuda.synchronize()
+        g.close()
+        return gy.cpu().numpy(), XR_grad.numpy().copy(), float(gh)
+
+    ref = run()
+    for kw in ({"split": 1200}, {"split": 2048}, {"serial": True}, {"streams": True}):
+        got = run(**kw)
+        print(kw, flush=True)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], kw
+    rloss, ry, rX, rh = G.loss_and_grads(Phi, h2, XL, y, XR.T)
+    elementwise_close(ref[0], ry, TOL_G)
+    elementwise_close(ref[1], rX.T, TOL_G)
+    assert ref[2] == pytest.approx(rh, rel=TOL_G)
+
+
+def test_streamed_vjp_arbitrary_cotangents_without_xr_grad():
+    n, m = 280, 450
+    Phi, h2, XL, y, XR = _problem(n, 4, m, seed=4, h2=0.35)
+    rng = np.random.default_rng(1)
+    bb, sb, vb = rng.standard_normal((m, 4)), rng.standard_normal(m), rng.standard_normal(m)
+    g = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=64, keep_for_grad=True)
+    XR_host = torch.tensor(XR).pin_memory()
+    g.stream(XR_host)
+    g.stream_backward(XR_host, *(torch.tensor(a).pin_memory() for a in (bb, sb, vb)))
+    gy, gh = g.backward_finish()
+    torch.cuda.synchronize()
+    g.close()
+    ry, _, rh = G.outputs_grads(Phi, h2, XL, y, XR.T, bb, sb, vb)
+    elementwise_close(gy.cpu().numpy(), ry, TOL_G)
+    assert float(gh) == pytest.approx(rh, rel=TOL_G)
+
+
+def test_stream_backward_errors():
+    Phi, h2, XL, y, XR = _problem(200, 4, 100, seed=2, h2=0.4)
+    XR_host = torch.tensor(XR).pin_memory()
+    z = [torch.zeros(100, 4, dtype=torch.float64), torch.zeros(100, dtype=torch.float64),
+         torch.zeros(100, dtype=torch.float64)]
+    g = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=64)
+    with pytest.raises(GLSError) as e:
+        g.stream_backward(XR_host, *z)
+    assert "GLS_KEEP_FOR_GRAD" in str(e.value)
+    g.close()
+    g = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=64, keep_for_grad=True)
+    with pytest.raises(GLSError):
+        g.stream_backward(XR_host, *z, col0=101)
+    with pytest.raises(ValueError):
+        g.stream_backward(XR_host, z[0][:50], z[1], z[2])
+    s = g.stream_backward(XR_host, *z, col0=100)   # empty: nothing streamed
+    assert s.blocks == 0
+    g.close()
