@@ -334,6 +334,72 @@ def measure_scale(args, dev):
     return res
 
 
+def measure_scale_grad(args, dev):
+    """d loss / d h2 and d loss / d y of the loss sum_i t_i^2 over a whole large
+    study whose SNPs stay in host memory (m = 2,000,000 at n = 20,000): per pass
+    over a pinned pool of distinct SNP blocks (about 21 GB), the forward stream
+    (gls_stream), the loss's cotangents on the device, and the streamed adjoint
+    (gls_stream_backward); after m SNPs, gls_backward_finish.  Setup included;
+    peak device memory recorded."""
+    import torch
+
+    from paper_1302_4332_amd import synth
+    from paper_1302_4332_amd.gls import GLSContext, t2_loss
+
+    w = synth.WORKLOADS[args.scale_grad]
+    n, p, bc = w.n, w.p, w.block_cols
+    pool = min(w.m, max(bc, int(21e9 / (8 * n)) // bc * bc))
+    st = synth.make_study(w, m=pool)
+    host = torch.empty((pool, n), dtype=torch.float64).pin_memory()
+    CH = 16384
+    for j0 in range(0, pool, CH):
+        j1 = min(pool, j0 + CH)
+        host[j0:j1] = torch.from_numpy(synth.genotypes_u8(n, j0, j1, w.seed)).to(torch.float64)
+    Phi_d, XL_d, y_d = (torch.tensor(np.ascontiguousarray(a), device=dev) for a in (st.Phi, st.XL, st.y))
+    pin = lambda *shape: torch.empty(shape, dtype=torch.float64).pin_memory()
+    out = (pin(pool, p), pin(pool), pin(pool), torch.empty(pool, dtype=torch.int32).pin_memory())
+    cot = (pin(pool, p), pin(pool), pin(pool))
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    ctx = GLSContext(Phi_d, w.h2, XL_d, y_d, block_cols=bc, precision=args.grad_precision,
+                     refine_sweeps=args.grad_sweeps, keep_for_grad=True)
+    done, loss, fwd_ms, bwd_ms, passes = 0, 0.0, 0.0, 0.0, []
+    while done < w.m:
+        k = min(pool, w.m - done)
+        tp = time.perf_counter()
+        _, sf = ctx.stream(host[:k], out=tuple(o[:k] for o in out))
+        leaves = [o[:k].to(dev).requires_grad_(True) for o in out[:3]]
+        value = t2_loss(*leaves)
+        for c, g in zip(cot, torch.autograd.grad(value, leaves)):
+            c[:k].copy_(g)
+        loss += float(value.detach())
+        sb = ctx.stream_backward(host[:k], *(c[:k] for c in cot))
+        fwd_ms += sf.wall_ms
+        bwd_ms += sb.wall_ms
+        done += k
+        passes.append({"snps": k, "ms": round((time.perf_counter() - tp) * 1e3, 1), "forward_wall_ms": round(sf.wall_ms, 1),
+                       "backward_wall_ms": round(sb.wall_ms, 1), "backward_compute_ms": round(sb.compute_ms, 1)})
+        log(f"grad pass {len(passes)}: {done:,} of {w.m:,} SNPs, forward {sf.wall_ms:.0f} ms, "
+            f"backward {sb.wall_ms:.0f} ms")
+    y_grad, h2_grad = ctx.backward_finish()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ctx.close()
+    peak = int(torch.cuda.max_memory_allocated())
+    mem = int(torch.cuda.get_device_properties(0).total_memory)
+    res = {"workload": w.name, "n": n, "p": p, "m": w.m, "block_cols": bc, "precision": args.grad_precision,
+           "refine_sweeps": args.grad_sweeps, "pool_snps": pool, "loss": loss, "h2_grad": float(h2_grad),
+           "y_grad_norm": float(torch.linalg.norm(y_grad)), "seconds": total, "snps_per_s": w.m / total,
+           "forward_wall_ms": fwd_ms, "backward_wall_ms": bwd_ms, "passes": passes,
+           "peak_device_bytes": peak, "device_bytes": mem, "peak_fraction": peak / mem,
+           "note": "setup, forward stream, loss cotangents, streamed adjoint and finish; a pinned pool of distinct "
+                   "SNPs streamed repeatedly"}
+    log(f"scale grad {w.name}: {w.m:,} SNPs forward + backward in {total:.1f} s, d loss/d h2 {float(h2_grad):.6e}, "
+        f"peak device memory {peak / 1e9:.1f} GB ({peak / mem:.1%})")
+    return res
+
+
 def measure_resident(args, Phi_d, XL_d, y_d, X_d, m, n, p, bc, h2, steps):
     """The whole study with the SNP matrix already in HBM, setup included:
     setup, every block, results copied to host memory."""
@@ -447,6 +513,10 @@ def main():
                     help="timed runs of each forms / bytes / adjoint measurement (the median is reported)")
     ap.add_argument("--scale", default=None,
                     help="also stream a whole large workload (e.g. c2_n10k_m1M) from a cycled pinned pool")
+    ap.add_argument("--scale-grad", default=None,
+                    help="also compute d loss / d h2 over a whole large streamed workload (e.g. c4_n20k_p8)")
+    ap.add_argument("--grad-precision", default="fp32_ir", help="precision of the --scale-grad study")
+    ap.add_argument("--grad-sweeps", type=int, default=2, help="refinement sweeps of the --scale-grad study")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -585,6 +655,8 @@ def main():
     del X_d
     if args.scale:
         out["scale"] = measure_scale(args, dev)
+    if args.scale_grad:
+        out["scale_grad"] = measure_scale_grad(args, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity_vs_oracle"] = cpu_baselines(args, st, m, bc, h2, out_h[0].numpy(),
