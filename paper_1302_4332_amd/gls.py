@@ -423,6 +423,7 @@ def stream_grad(Phi, h2, XL, y, XR_host, loss, *, block_cols: int, precision="fp
     differentiated by torch on the device outputs, and the study is streamed
     again through the adjoint (gls_stream_backward, then gls_backward_finish).
     Returns (loss value, y_grad, h2_grad, (b, sigma2, v, status) host tensors)."""
+    _need(XR_host, "XR_host", cuda=False)   # the adjoint takes FP64 SNP values
     g = GLSContext(Phi, h2, XL, y, block_cols=block_cols, precision=precision, refine_sweeps=refine_sweeps,
                    keep_for_grad=True)
     try:
