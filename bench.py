@@ -347,6 +347,8 @@ def measure_scale_grad(args, dev):
     from paper_1302_4332_amd.gls import GLSContext, t2_loss
 
     w = synth.WORKLOADS[args.scale_grad]
+    if args.grad_m:
+        w = dataclasses.replace(w, m=args.grad_m)
     n, p, bc = w.n, w.p, w.block_cols
     pool = min(w.m, max(bc, int(21e9 / (8 * n)) // bc * bc))
     st = synth.make_study(w, m=pool)
@@ -517,6 +519,7 @@ def main():
                     help="also compute d loss / d h2 over a whole large streamed workload (e.g. c4_n20k_p8)")
     ap.add_argument("--grad-precision", default="fp32_ir", help="precision of the --scale-grad study")
     ap.add_argument("--grad-sweeps", type=int, default=2, help="refinement sweeps of the --scale-grad study")
+    ap.add_argument("--grad-m", type=int, default=None, help="override the SNP count of the --scale-grad study")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM traffic counters)")
     args = ap.parse_args()
