@@ -11,6 +11,9 @@ over SNP blocks held in page-locked host memory, then gls_backward_finish.
   and on caller-given streams.
 - Arbitrary cotangents of all three outputs against the reference VJP.
 - Error paths: no GLS_KEEP_FOR_GRAD, col0 outside [0, m], a wrong shape.
+- At n = 20,000, p = 8, blocks of 16,384 in refined FP32 x2 (the whole-study
+  gradient's configuration): bitwise equal to the resident adjoint on the first
+  block and the ragged last one.
 """
 import numpy as np
 import pytest
@@ -159,3 +162,30 @@ def test_stream_backward_errors():
     s = g.stream_backward(XR_host, *z, col0=100)   # empty: nothing streamed
     assert s.blocks == 0
     g.close()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_streamed_gradient_equals_resident():
+    """n = 20,000, p = 8, blocks of 16,384, refined FP32 x2 (the configuration of
+    the bench's whole-study gradient): the study's first block and its ragged
+    last 1,152 SNPs.  The stream opens with blocks of 2,048, 2,560, ... (all
+    multiples of 16), the resident path runs 16,384 and 1,152, so y_grad and
+    h2_grad agree bitwise; the resident h2 gradient of these SNPs is checked
+    against the oracle's central differences in test_gpu_combined.py."""
+    w = synth.WORKLOADS["c4_n20k_p8"]
+    st = synth.make_study(w)
+    bc, tail = w.block_cols, w.m % w.block_cols
+    Xh = np.concatenate([st.snps(0, bc), st.snps(w.m - tail, w.m)])
+    Phi, XL, y = _t(st.Phi), _t(st.XL), _t(st.y)
+    yt, Xt = _t(st.y, True), _t(Xh)
+    h2t = torch.tensor(w.h2, dtype=torch.float64, device=DEV, requires_grad=True)
+    b, s2, v = GLSFunction.apply(yt, Xt, h2t, Phi, XL, bc, "fp32_ir", 2)
+    t2_loss(b, s2, v).backward()
+    ry, rh = yt.grad.cpu().numpy(), float(h2t.grad)
+    del Xt, b, s2, v
+    loss, gy, gh, outs = stream_grad(Phi, w.h2, XL, y, torch.tensor(Xh).pin_memory(), t2_loss, block_cols=bc,
+                                     precision="fp32_ir", refine_sweeps=2)
+    print(f"n = 20,000: d loss / d h2 resident {rh:.12e} streamed {float(gh):.12e}", flush=True)
+    assert np.array_equal(gy.cpu().numpy(), ry)
+    assert float(gh) == rh
+    assert (outs[3].numpy() == 0).all()
