@@ -280,11 +280,12 @@ def measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, b_fp64_host):
 
 
 def measure_scale(args, dev):
-    """Streamed rate over a whole large study (m = 1,000,000 or 2,000,000): a
-    pinned pool of distinct SNP blocks (about 21 GB) is streamed untimed until
-    two passes agree, then again and again until the study's m SNPs have gone
-    through; the work per SNP is the same as for m distinct SNPs.  Setup
-    excluded."""
+    """Streamed rate over a whole large study (m = 1,000,000 or 2,000,000) in
+    the precision --precision / --sweeps name: a pinned pool of distinct SNP
+    blocks (about 21 GB) is streamed untimed until two passes agree, then again
+    and again until the study's m SNPs have gone through; the work per SNP is
+    the same as for m distinct SNPs.  Setup excluded.  For a refined precision
+    the last pass's b is compared with plain FP64 on the same SNPs."""
     import torch
 
     from paper_1302_4332_amd import synth
@@ -301,7 +302,7 @@ def measure_scale(args, dev):
         j1 = min(pool, j0 + CH)
         host[j0:j1] = torch.from_numpy(synth.genotypes_u8(n, j0, j1, w.seed)).to(torch.float64)
     Phi_d, XL_d, y_d = (torch.tensor(np.ascontiguousarray(a), device=dev) for a in (st.Phi, st.XL, st.y))
-    ctx = GLSContext(Phi_d, w.h2, XL_d, y_d, block_cols=bc)
+    ctx = GLSContext(Phi_d, w.h2, XL_d, y_d, block_cols=bc, precision=args.precision, refine_sweeps=args.sweeps)
     out = (torch.empty((pool, p), dtype=torch.float64).pin_memory(), torch.empty(pool, dtype=torch.float64).pin_memory(),
            torch.empty(pool, dtype=torch.float64).pin_memory(), torch.empty(pool, dtype=torch.int32).pin_memory())
     # warm-up: whole passes over the pool until two in a row agree within 3% in solve time (at most four; after
@@ -326,7 +327,19 @@ def measure_scale(args, dev):
         passes += 1
     total = time.perf_counter() - t0
     ctx.close()
+    err_vs_fp64 = None
+    if args.precision != "fp64":   # the pool's last outputs against plain FP64 on the same SNPs
+        k = min(pool, w.m - (passes - 1) * pool)
+        ref_ctx = GLSContext(Phi_d, w.h2, XL_d, y_d, block_cols=bc)
+        (rb, _, _, rst), _ = ref_ctx.stream(host[:k])
+        ref_ctx.close()
+        ok = (rst.numpy() == 0) & (out[3][:k].numpy() == 0)
+        rb, gb = rb.numpy()[ok], out[0][:k].numpy()[ok]
+        err_vs_fp64 = float(np.max(np.max(np.abs(gb - rb), axis=1) / np.max(np.abs(rb), axis=1)))
+        log(f"scale {w.name} {args.precision} x{args.sweeps}: max rel err of b against FP64 {err_vs_fp64:.2e} "
+            f"over {int(ok.sum()):,} SNPs")
     res = {"workload": w.name, "n": n, "p": p, "m": w.m, "block_cols": bc, "pool_snps": pool, "passes": passes,
+           "precision": args.precision, "refine_sweeps": args.sweeps, "max_rel_err_b_vs_fp64": err_vs_fp64,
            "snps_per_s": w.m / total, "snps_per_s_device_wall": w.m / (wall_ms / 1e3), "compute_ms": compute_ms,
            "pass_wall_compute_ms": pass_ms,
            "note": "PCIe-inclusive, setup excluded; a pinned pool of distinct SNPs streamed repeatedly"}
