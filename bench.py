@@ -347,6 +347,38 @@ def measure_scale(args, dev):
     return res
 
 
+def measure_gemm_ceiling(dev):
+    """The vendor library's dense products (torch.matmul, which calls hipBLASLt or
+    rocBLAS) on contiguous operands at the per-block shape M = K = 10,240,
+    N = 8,192: a measured ceiling for each matrix-core precision beside the
+    datasheet peak.  Measurement only; no product of the solver goes through it."""
+    import torch
+
+    M, N, K = 10240, 8192, 10240
+    res = {"shape_mnk": [M, N, K], "library": "torch.matmul (hipBLASLt / rocBLAS)"}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("fp16", torch.float16),
+                     ("bf16", torch.bfloat16)):
+        g = torch.Generator(device=dev).manual_seed(5)
+        A = torch.rand((M, K), device=dev, dtype=dt, generator=g)
+        B = torch.rand((K, N), device=dev, dtype=dt, generator=g)
+        C = torch.matmul(A, B)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            torch.matmul(A, B, out=C)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * M * N * K / (ms / 1e3) / 1e12
+        peak = PEAK_TFLOPS[{"fp64": "fp64", "fp32": "fp32_ir", "fp16": "fp16_ir", "bf16": "bf16_ir"}[name]]
+        res[name] = {"ms": ms, "tflops": tf, "peak": peak, "frac": tf / peak}
+        log(f"vendor dense {name} product {M}x{N}x{K}: {ms:.2f} ms, {tf:.1f} TFLOP/s ({tf / peak:.2f} of peak)")
+        del A, B, C
+    return res
+
+
 def measure_scale_grad(args, dev):
     """d loss / d h2 and d loss / d y of the loss sum_i t_i^2 over a whole large
     study whose SNPs stay in host memory (m = 2,000,000 at n = 20,000): per pass
@@ -526,6 +558,7 @@ def main():
     ap.add_argument("--no-bytes", action="store_true", help="skip the genotype-byte and packed-dosage measurements")
     ap.add_argument("--sub-reps", type=int, default=3,
                     help="timed runs of each forms / bytes / adjoint measurement (the median is reported)")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the vendor-library dense product ceilings")
     ap.add_argument("--scale", default=None,
                     help="also stream a whole large workload (e.g. c2_n10k_m1M) from a cycled pinned pool")
     ap.add_argument("--scale-grad", default=None,
@@ -669,6 +702,8 @@ def main():
     if not args.no_bytes:
         out["bytes"] = measure_bytes(args, st, Phi_d, XL_d, y_d, X_d, m, dev, out_h[0])
     del X_d
+    if not args.no_ceiling:
+        out["gemm_ceiling"] = measure_gemm_ceiling(dev)
     if args.scale:
         out["scale"] = measure_scale(args, dev)
     if args.scale_grad:
