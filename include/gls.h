@@ -274,6 +274,22 @@ gls_status gls_stream_backward(gls_handle h, int64_t m, int64_t col0,
                                void* compute_stream, void* copy_stream,
                                gls_stream_stats* stats_out);
 
+/* gls_stream_backward for a SNP matrix read from storage (both buffering
+ * levels of Sec. 3.1): the file, offset, elem_bits (64 FP64, 8 genotype
+ * bytes, 2 packed 2-bit dosages), block schedule, reader thread, host_ws
+ * (page-locked, gls_stream_file_host_bytes(h, elem_bits) bytes) and streams
+ * are those of gls_stream_file.  Byte and packed columns are widened to FP64
+ * on the device before each block's adjoint.  Cotangents as in
+ * gls_stream_backward; XR_grad_host, if not NULL, receives dL/dX_R as n x m
+ * FP64 (ld n) in host memory.  Requires GLS_KEEP_FOR_GRAD (else
+ * GLS_ERR_STATE); read errors and argument errors as for gls_stream_file. */
+gls_status gls_stream_backward_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bits,
+                                    int64_t m, int64_t col0, void* host_ws, size_t host_ws_bytes,
+                                    const double* b_bar_host, const double* sigma2_bar_host,
+                                    const double* v_bar_host, double* XR_grad_host,
+                                    void* compute_stream, void* copy_stream,
+                                    gls_stream_stats* stats_out);
+
 /* Per-phase device time of the block path, measured with HIP events recorded
  * around each phase's kernels on the caller's stream while profiling is on.
  *   phase 0: triangular product X~_R,b = L^-1 X_R,b (plain, or the

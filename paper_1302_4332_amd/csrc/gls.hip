@@ -1116,6 +1116,17 @@ static void ozaki_product(Ctx* c, int mb, hipStream_t s) {
                      dim3(OZ_THREADS), 0, s, a);
 }
 
+// Dosage bytes (or packed 2-bit dosages) of a block widened into the zero-padded FP64 buffer x64 (ld N).
+void widen_u8(Ctx* c, const uint8_t* G, int64_t ldg, int mb, hipStream_t s) {
+  const int64_t N = c->N;
+  hipLaunchKernelGGL(u8_to_f64_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->x64);
+}
+void widen_u2(Ctx* c, const uint8_t* G2, int64_t ldg, int mb, hipStream_t s) {
+  const int64_t N = c->N;
+  hipLaunchKernelGGL(unpack_u2_f64_kernel, dim3(grid_for(N / 4 * mb)), dim3(256), 0, s, G2, ldg, (int)c->n, (int)N,
+                     mb, c->x64);
+}
+
 gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, double* b, int64_t ld_b, double* s2,
                             double* v, int* st, hipStream_t s) {
   const int64_t N = c->N;
@@ -1129,7 +1140,7 @@ gls_status block_forward_u8(Ctx* c, int mb, const uint8_t* G, int64_t ldg, doubl
     snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
     return GLS_OK;
   }
-  hipLaunchKernelGGL(u8_to_f64_kernel, dim3(grid_for(N * mb)), dim3(256), 0, s, G, ldg, (int)c->n, (int)N, mb, c->x64);
+  widen_u8(c, G, ldg, mb, s);
   return block_forward(c, mb, c->x64, N, b, ld_b, s2, v, st, s);
 }
 
@@ -1147,8 +1158,7 @@ gls_status block_forward_u2(Ctx* c, int mb, const uint8_t* G2, int64_t ldg, doub
     snp_reduce_solve(c, c->Xt, mb, b, ld_b, s2, v, st, s);
     return GLS_OK;
   }
-  hipLaunchKernelGGL(unpack_u2_f64_kernel, dim3(grid_for(N / 4 * mb)), dim3(256), 0, s, G2, ldg, (int)c->n, (int)N,
-                     mb, c->x64);
+  widen_u2(c, G2, ldg, mb, s);
   return block_forward(c, mb, c->x64, N, b, ld_b, s2, v, st, s);
 }
 

@@ -142,5 +142,7 @@ gls_status block_forward_u2(Ctx* c, int mb, const uint8_t* G2, int64_t ldg, doub
                             double* v, int* st, hipStream_t s);
 gls_status block_backward(Ctx* c, int mb, const double* XR, int64_t ld_xr, const double* bbar, const double* s2bar,
                           const double* vbar, double* XR_grad, hipStream_t s);
+void widen_u8(Ctx* c, const uint8_t* G, int64_t ldg, int mb, hipStream_t s);
+void widen_u2(Ctx* c, const uint8_t* G2, int64_t ldg, int mb, hipStream_t s);
 
 }  // namespace gls

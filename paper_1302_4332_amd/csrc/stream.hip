@@ -425,12 +425,87 @@ size_t host_ring_bytes(const Ctx* c, int64_t col_bytes) {
   return 3 * ((one + 4095) / 4096 * 4096);
 }
 
+// The work a file stream does on each block once its columns are in device buffer X (rows elements per column,
+// dense), on the compute stream: the forward solve and its results, or the adjoint.
 template <typename T>
-gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t col0, char* host,
-                            double* b_host, double* sigma2_host, double* v_host, int32_t* status_host,
+struct FileForward {
+  double* b_host;
+  double* sigma2_host;
+  double* v_host;
+  int32_t* status_host;
+  gls_status block(Ctx* c, const T* X, int64_t rows, int64_t, int64_t cols, hipStream_t sc, gls_stream_stats*) const {
+    return solve_block(c, (int)cols, X, rows, c->ob, c->p, c->os2, c->ov, c->ost, sc);
+  }
+  // results of the block, after its timing event
+  hipError_t after(Ctx* c, int64_t col, int64_t cols, hipStream_t sc, gls_stream_stats* st) const {
+    const int p = c->p;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(b_host + col * p, c->ob, sizeof(double) * p * cols, hipMemcpyDeviceToHost, sc)) ||
+        (e = hipMemcpyAsync(sigma2_host + col, c->os2, sizeof(double) * cols, hipMemcpyDeviceToHost, sc)) ||
+        (e = hipMemcpyAsync(v_host + col, c->ov, sizeof(double) * cols, hipMemcpyDeviceToHost, sc)) ||
+        (e = hipMemcpyAsync(status_host + col, c->ost, sizeof(int32_t) * cols, hipMemcpyDeviceToHost, sc)))
+      return e;
+    st->d2h_bytes += (int64_t)(sizeof(double) * (p + 2) + sizeof(int32_t)) * cols;
+    return hipSuccess;
+  }
+};
+
+// FP64 columns of a block for the adjoint: FP64 input as it is, bytes and packed dosages widened into the
+// handle's zero-padded FP64 staging buffer.
+const double* fp64_columns(Ctx*, const double* X, int64_t rows, int64_t, hipStream_t, int64_t* ld) {
+  *ld = rows;
+  return X;
+}
+const double* fp64_columns(Ctx* c, const uint8_t* X, int64_t rows, int64_t cols, hipStream_t s, int64_t* ld) {
+  widen_u8(c, X, rows, (int)cols, s);
+  *ld = c->N;
+  return c->x64;
+}
+const double* fp64_columns(Ctx* c, const Packed2* X, int64_t rows, int64_t cols, hipStream_t s, int64_t* ld) {
+  widen_u2(c, reinterpret_cast<const uint8_t*>(X), rows, (int)cols, s);
+  *ld = c->N;
+  return c->x64;
+}
+
+template <typename T>
+struct FileBackward {
+  const double* bbar_host;
+  const double* s2bar_host;
+  const double* vbar_host;
+  double* XR_grad_host;   // n x m, ld n, or NULL
+  gls_status block(Ctx* c, const T* X, int64_t rows, int64_t col, int64_t cols, hipStream_t sc,
+                   gls_stream_stats* st) const {
+    const int p = c->p;
+    struct {
+      void* dst;
+      const void* src;
+      size_t bytes;
+    } up[3] = {{c->ob, bbar_host + col * p, sizeof(double) * p * cols},
+               {c->os2, s2bar_host + col, sizeof(double) * cols},
+               {c->ov, vbar_host + col, sizeof(double) * cols}};
+    for (int q = 0; q < 3; ++q) {
+      const hipError_t e = hipMemcpyAsync(up[q].dst, up[q].src, up[q].bytes, hipMemcpyHostToDevice, sc);
+      if (e != hipSuccess) return hip_fail(e, "gls_stream_backward_file: cotangent H2D");
+      st->h2d_bytes += (int64_t)up[q].bytes;
+    }
+    int64_t ld = 0;
+    const double* Xd = fp64_columns(c, X, rows, cols, sc, &ld);
+    return block_backward(c, (int)cols, Xd, ld, c->ob, c->os2, c->ov, nullptr, sc);
+  }
+  hipError_t after(Ctx* c, int64_t col, int64_t cols, hipStream_t sc, gls_stream_stats* st) const {
+    if (!XR_grad_host) return hipSuccess;
+    // X_R bar of the block stays in Xb (ld N) until the next block's adjoint, queued behind this copy
+    const hipError_t e = hipMemcpy2DAsync(XR_grad_host + col * c->n, sizeof(double) * c->n, c->Xb,
+                                          sizeof(double) * c->N, sizeof(double) * c->n, cols, hipMemcpyDeviceToHost, sc);
+    if (e == hipSuccess) st->d2h_bytes += (int64_t)sizeof(double) * c->n * cols;
+    return e;
+  }
+};
+
+template <typename T, typename Op>
+gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t col0, char* host, const Op& op,
                             hipStream_t sc, hipStream_t sx_in, gls_stream_stats* stats_out) {
   const int64_t bc = c->bc, rows = col_elems(c, (const T*)nullptr);
-  const int p = c->p;
   const bool serial = (c->opts.flags & GLS_STREAM_SERIAL) != 0;
   hipStream_t sx = serial ? sc : sx_in;
   const std::vector<int64_t> bstart = block_schedule(bc, m - col0);   // opening ramp as in gls_stream
@@ -534,17 +609,12 @@ gls_status stream_file_impl(Ctx* c, int fd, int64_t offset, int64_t m, int64_t c
     st.h2d_bytes += (int64_t)sizeof(T) * rows * cols;
     if ((e = hipStreamWaitEvent(sc, ev_h2d(blk), 0)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: wait"));
     if ((e = hipEventRecord(pool.ev[2 * blk], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
-    gls_status r =
-        solve_block(c, (int)cols, stage(c, cur, (const T*)nullptr), rows, c->ob, p, c->os2, c->ov, c->ost, sc);
+    gls_status r = op.block(c, stage(c, cur, (const T*)nullptr), rows, col, cols, sc, &st);
     if (r != GLS_OK) return fail(r);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: launch"));
     if ((e = hipEventRecord(c->ev_comp[cur], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
     if ((e = hipEventRecord(pool.ev[2 * blk + 1], sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: record"));
-    if ((e = hipMemcpyAsync(b_host + col * p, c->ob, sizeof(double) * p * cols, hipMemcpyDeviceToHost, sc)) ||
-        (e = hipMemcpyAsync(sigma2_host + col, c->os2, sizeof(double) * cols, hipMemcpyDeviceToHost, sc)) ||
-        (e = hipMemcpyAsync(v_host + col, c->ov, sizeof(double) * cols, hipMemcpyDeviceToHost, sc)) ||
-        (e = hipMemcpyAsync(status_host + col, c->ost, sizeof(int32_t) * cols, hipMemcpyDeviceToHost, sc)))
-      return fail(hip_fail(e, "gls_stream_file: D2H"));
-    st.d2h_bytes += (int64_t)(sizeof(double) * (p + 2) + sizeof(int32_t)) * cols;
+    if ((e = op.after(c, col, cols, sc, &st)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: D2H"));
     if (serial) {
       if ((e = hipStreamSynchronize(sc)) != hipSuccess) return fail(hip_fail(e, "gls_stream_file: synchronize"));
     } else if (blk >= 1) {
@@ -624,14 +694,60 @@ extern "C" gls_status gls_stream_file(gls_handle h, const char* path, int64_t of
   const hipStream_t sc = rs.sc, sx = rs.sx;
   char* ring = static_cast<char*>(host_ws);
   if (elem_bits == 64)
-    st = stream_file_impl<double>(c, fd, offset, m, col0, ring, b_host, sigma2_host, v_host, status_host, sc, sx,
-                                  stats_out);
+    st = stream_file_impl<double>(c, fd, offset, m, col0, ring,
+                                  FileForward<double>{b_host, sigma2_host, v_host, status_host}, sc, sx, stats_out);
   else if (elem_bits == 8)
-    st = stream_file_impl<uint8_t>(c, fd, offset, m, col0, ring, b_host, sigma2_host, v_host, status_host, sc, sx,
-                                   stats_out);
+    st = stream_file_impl<uint8_t>(c, fd, offset, m, col0, ring,
+                                   FileForward<uint8_t>{b_host, sigma2_host, v_host, status_host}, sc, sx, stats_out);
   else
-    st = stream_file_impl<Packed2>(c, fd, offset, m, col0, ring, b_host, sigma2_host, v_host, status_host, sc, sx,
-                                   stats_out);
+    st = stream_file_impl<Packed2>(c, fd, offset, m, col0, ring,
+                                   FileForward<Packed2>{b_host, sigma2_host, v_host, status_host}, sc, sx, stats_out);
+  close(fd);
+  return st;
+}
+
+extern "C" gls_status gls_stream_backward_file(gls_handle h, const char* path, int64_t offset, int32_t elem_bits,
+                                               int64_t m, int64_t col0, void* host_ws, size_t host_ws_bytes,
+                                               const double* b_bar_host, const double* sigma2_bar_host,
+                                               const double* v_bar_host, double* XR_grad_host, void* compute_stream,
+                                               void* copy_stream, gls_stream_stats* stats_out) {
+  Ctx* c = h;
+  if (!c || !c->ready || !c->grad) {
+    set_last_error_str("gls_stream_backward_file: handle not set up with GLS_KEEP_FOR_GRAD");
+    return GLS_ERR_STATE;
+  }
+  if (!path || offset < 0 || m < 0 || col0 < 0 || col0 > m)
+    return arg_fail("gls_stream_backward_file: bad path/offset/m/col0");
+  if (file_col_bytes(c, elem_bits) == 0) return arg_fail("gls_stream_backward_file: elem_bits must be 64, 8 or 2");
+  if (col0 == m) {
+    if (stats_out) *stats_out = gls_stream_stats{};
+    return GLS_OK;
+  }
+  if (!host_ws || host_ws_bytes < host_ring_bytes(c, file_col_bytes(c, elem_bits)))
+    return arg_fail("gls_stream_backward_file: host_ws smaller than gls_stream_file_host_bytes()");
+  if (!b_bar_host || !sigma2_bar_host || !v_bar_host) return arg_fail("gls_stream_backward_file: NULL cotangent");
+  const int fd = open(path, O_RDONLY);
+  if (fd < 0) return arg_fail("gls_stream_backward_file: cannot open the file");
+  RunStreams rs;
+  const hipError_t e = run_streams(c, compute_stream, copy_stream, &rs);
+  if (e != hipSuccess) {
+    close(fd);
+    return hip_fail(e, "gls_stream_backward_file: stream order");
+  }
+  char* ring = static_cast<char*>(host_ws);
+  gls_status st;
+  if (elem_bits == 64)
+    st = stream_file_impl<double>(c, fd, offset, m, col0, ring,
+                                  FileBackward<double>{b_bar_host, sigma2_bar_host, v_bar_host, XR_grad_host}, rs.sc,
+                                  rs.sx, stats_out);
+  else if (elem_bits == 8)
+    st = stream_file_impl<uint8_t>(c, fd, offset, m, col0, ring,
+                                   FileBackward<uint8_t>{b_bar_host, sigma2_bar_host, v_bar_host, XR_grad_host},
+                                   rs.sc, rs.sx, stats_out);
+  else
+    st = stream_file_impl<Packed2>(c, fd, offset, m, col0, ring,
+                                   FileBackward<Packed2>{b_bar_host, sigma2_bar_host, v_bar_host, XR_grad_host},
+                                   rs.sc, rs.sx, stats_out);
   close(fd);
   return st;
 }

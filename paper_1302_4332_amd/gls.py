@@ -80,6 +80,8 @@ SIGNATURES = {
     "gls_backward_finish": (ctypes.c_int, [_P, _P, _P, _P]),
     "gls_stream_backward": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
                                            ctypes.POINTER(GlsStreamStats)]),
+    "gls_stream_backward_file": (ctypes.c_int, [_P, ctypes.c_char_p, _I64, _I32, _I64, _I64, _P, ctypes.c_size_t,
+                                                _P, _P, _P, _P, _P, _P, ctypes.POINTER(GlsStreamStats)]),
     "gls_profile_enable": (ctypes.c_int, [_P, _I32]),
     "gls_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(GlsPhaseStats), _I32]),
     "gls_destroy": (None, [_P]),
@@ -402,6 +404,29 @@ class GLSContext:
         xs = self._use(copy_stream) if copy_stream is not None else ctypes.c_void_p(None)
         st = lib().gls_stream_backward(self.handle, m, col0, _ptr(XR_host), self.n, _ptr(b_bar), _ptr(sigma2_bar),
                                        _ptr(v_bar), _ptr(XR_grad), self._use(cs), xs, ctypes.byref(stats))
+        _check(st)
+        return stats
+
+    def stream_backward_file(self, path: str, m: int, b_bar, sigma2_bar, v_bar, fmt=torch.float64, offset: int = 0,
+                             col0: int = 0, XR_grad=None, host_ws=None, compute_stream=None, copy_stream=None):
+        """stream_backward for SNPs [col0, m) read from a SNP-major file, in the
+        formats of stream_file (torch.float64, torch.uint8 or "u2"); XR_grad, if
+        given, is a host tensor (m, n) float64.  Returns the stats struct."""
+        elem = _FILE_BITS[fmt]
+        for t, name, shape in ((b_bar, "b_bar", (m, self.p)), (sigma2_bar, "sigma2_bar", (m,)), (v_bar, "v_bar", (m,))) + (
+                ((XR_grad, "XR_grad", (m, self.n)),) if XR_grad is not None else ()):
+            _need(t, name, cuda=False)
+            if t.is_cuda or tuple(t.shape) != shape:
+                raise ValueError(f"{name} must be a host tensor of shape {shape}")
+        need = int(lib().gls_stream_file_host_bytes(self.handle, elem))
+        if host_ws is None or host_ws.numel() < need:
+            host_ws = torch.empty(need, dtype=torch.uint8).pin_memory()
+        stats = GlsStreamStats()
+        cs = compute_stream or torch.cuda.current_stream()
+        xs = self._use(copy_stream) if copy_stream is not None else ctypes.c_void_p(None)
+        st = lib().gls_stream_backward_file(self.handle, path.encode(), offset, elem, m, col0, _ptr(host_ws),
+                                            host_ws.numel(), _ptr(b_bar), _ptr(sigma2_bar), _ptr(v_bar),
+                                            _ptr(XR_grad), self._use(cs), xs, ctypes.byref(stats))
         _check(st)
         return stats
 

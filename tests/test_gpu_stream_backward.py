@@ -189,3 +189,89 @@ def test_full_size_streamed_gradient_equals_resident():
     assert np.array_equal(gy.cpu().numpy(), ry)
     assert float(gh) == rh
     assert (outs[3].numpy() == 0).all()
+
+
+@pytest.fixture(scope="module")
+def snp_files(tmp_path_factory):
+    """The same 2,600 SNPs at n = 330 as an FP64 file behind a 24-byte header,
+    a byte file and a packed 2-bit file (blocks of 2,048: the opening ramp of
+    256, 320, 448, ... runs through the file as in memory)."""
+    n, m = 330, 2600
+    Phi, h2, XL, y, XR = _problem(n, 4, m, seed=21, h2=0.35)
+    G = XR.astype(np.uint8)
+    d = tmp_path_factory.mktemp("adj")
+    f64, u8, u2 = str(d / "x.f64"), str(d / "x.u8"), str(d / "x.u2")
+    with open(f64, "wb") as f:
+        f.write(b"\0" * 24)
+        f.write(XR.tobytes())
+    G.tofile(u8)
+    synth.pack_dosages_2bit(G).tofile(u2)
+    return Phi, h2, XL, y, XR, f64, u8, u2
+
+
+def _file_grads(snp_files, fmt, path, offset=0, serial=False, split=None, with_xr=True):
+    Phi, h2, XL, y, XR, *_ = snp_files
+    m, n = XR.shape
+    g, (bb, sb, vb) = _cotangents(Phi, h2, XL, y, torch.tensor(XR).pin_memory(), 2048, "fp64", 0,
+                                  serial_stream=serial)
+    XR_grad = torch.zeros((m, n), dtype=torch.float64).pin_memory() if with_xr else None
+    if split is None:
+        s = g.stream_backward_file(path, m, bb, sb, vb, fmt=fmt, offset=offset, XR_grad=XR_grad)
+        assert s.file_bytes == m * {torch.float64: 8 * n, torch.uint8: n, "u2": (n + 3) // 4}[fmt]
+    else:
+        g.stream_backward_file(path, split, bb[:split], sb[:split], vb[:split], fmt=fmt, offset=offset,
+                               XR_grad=XR_grad[:split] if with_xr else None)
+        g.stream_backward_file(path, m, bb, sb, vb, fmt=fmt, offset=offset, col0=split, XR_grad=XR_grad)
+    gy, gh = g.backward_finish()
+    torch.cuda.synchronize()
+    g.close()
+    return gy.cpu().numpy(), (XR_grad.numpy().copy() if with_xr else None), float(gh)
+
+
+def test_file_adjoint_equals_memory_adjoint(snp_files):
+    """FP64, byte and packed files, overlapped, serial and resumed: bitwise the
+    gradients of the in-memory streamed adjoint on the same values."""
+    Phi, h2, XL, y, XR, f64, u8, u2 = snp_files
+    g, (bb, sb, vb) = _cotangents(Phi, h2, XL, y, torch.tensor(XR).pin_memory(), 2048, "fp64", 0)
+    XR_host = torch.tensor(XR).pin_memory()
+    XR_grad = torch.zeros_like(XR_host).pin_memory()
+    g.stream_backward(XR_host, bb, sb, vb, XR_grad=XR_grad)
+    ry, rh = g.backward_finish()
+    torch.cuda.synchronize()
+    g.close()
+    ref = (ry.cpu().numpy(), XR_grad.numpy().copy(), float(rh))
+    cases = [dict(fmt=torch.float64, path=f64, offset=24), dict(fmt=torch.float64, path=f64, offset=24, serial=True),
+             dict(fmt=torch.float64, path=f64, offset=24, split=1024), dict(fmt=torch.uint8, path=u8),
+             dict(fmt="u2", path=u2), dict(fmt="u2", path=u2, serial=True, with_xr=False)]
+    for kw in cases:
+        gy, gX, gh = _file_grads(snp_files, **kw)
+        print({k: str(v) for k, v in kw.items() if k != "path"}, flush=True)
+        assert np.array_equal(gy, ref[0]) and gh == ref[2], kw
+        if gX is not None:
+            assert np.array_equal(gX, ref[1]), kw
+    rloss, ry_o, rX_o, rh_o = G.loss_and_grads(Phi, h2, XL, y, XR.T)
+    elementwise_close(ref[0], ry_o, TOL_G)
+    elementwise_close(ref[1], rX_o.T, TOL_G)
+    assert ref[2] == pytest.approx(rh_o, rel=TOL_G)
+
+
+def test_file_adjoint_errors(snp_files, tmp_path):
+    Phi, h2, XL, y, XR, f64, u8, u2 = snp_files
+    m = XR.shape[0]
+    z = [torch.zeros(m, 4, dtype=torch.float64), torch.zeros(m, dtype=torch.float64),
+         torch.zeros(m, dtype=torch.float64)]
+    g = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=2048)
+    with pytest.raises(GLSError, match="GLS_KEEP_FOR_GRAD"):
+        g.stream_backward_file(u8, m, *z, fmt=torch.uint8)
+    g.close()
+    g = GLSContext(_t(Phi), h2, _t(XL), _t(y), block_cols=2048, keep_for_grad=True)
+    with pytest.raises(GLSError, match="cannot open"):
+        g.stream_backward_file(str(tmp_path / "missing.u8"), m, *z, fmt=torch.uint8)
+    short = str(tmp_path / "short.u8")
+    XR[: m // 2].astype(np.uint8).tofile(short)
+    with pytest.raises(GLSError, match="shorter"):
+        g.stream_backward_file(short, m, *z, fmt=torch.uint8)
+    with pytest.raises(GLSError):
+        g.stream_backward_file(u8, m, *z, fmt=torch.uint8, col0=m + 1)
+    assert g.stream_backward_file(u8, m, *z, fmt=torch.uint8, col0=m).blocks == 0
+    g.close()
