@@ -467,6 +467,32 @@ def stream_grad(Phi, h2, XL, y, XR_host, loss, *, block_cols: int, precision="fp
     return float(value.detach()), y_grad, h2_grad, outs
 
 
+def stream_grad_file(Phi, h2, XL, y, path: str, m: int, loss, *, block_cols: int, fmt=torch.float64,
+                     offset: int = 0, precision="fp64", refine_sweeps: int = 0, XR_grad=None):
+    """stream_grad for a study whose SNPs are read from a SNP-major file (the
+    formats of GLSContext.stream_file): the forward stream and the adjoint each
+    read the file once (gls_stream_file, gls_stream_backward_file).  Returns
+    (loss value, y_grad, h2_grad, (b, sigma2, v, status) host tensors)."""
+    g = GLSContext(Phi, h2, XL, y, block_cols=block_cols, precision=precision, refine_sweeps=refine_sweeps,
+                   keep_for_grad=True)
+    try:
+        need = int(lib().gls_stream_file_host_bytes(g.handle, _FILE_BITS[fmt]))
+        host_ws = torch.empty(need, dtype=torch.uint8).pin_memory()
+        outs, _ = g.stream_file(path, m, fmt, offset=offset, host_ws=host_ws)
+        dev = Phi.device
+        leaves = [t.to(dev).requires_grad_(True) for t in outs[:3]]
+        value = loss(*leaves)
+        grads = torch.autograd.grad(value, leaves, allow_unused=True)
+        cot = [torch.zeros_like(t) if gr is None else gr for t, gr in zip(leaves, grads)]
+        cot = [c.detach().cpu().pin_memory() for c in cot]
+        g.stream_backward_file(path, m, *cot, fmt=fmt, offset=offset, XR_grad=XR_grad, host_ws=host_ws)
+        y_grad, h2_grad = g.backward_finish()
+        torch.cuda.current_stream().synchronize()
+    finally:
+        g.close()
+    return float(value.detach()), y_grad, h2_grad, outs
+
+
 class GLSFunction(torch.autograd.Function):
     """(b, sigma2, v) of every SNP as a differentiable function of y, X_R and h2.
 

@@ -21,7 +21,7 @@ import torch
 
 from oracle import gls_grad as G
 from paper_1302_4332_amd import synth
-from paper_1302_4332_amd.gls import GLSContext, GLSError, GLSFunction, stream_grad, t2_loss
+from paper_1302_4332_amd.gls import GLSContext, GLSError, GLSFunction, stream_grad, stream_grad_file, t2_loss
 from parity_util import elementwise_close
 
 pytestmark = pytest.mark.gpu
@@ -275,3 +275,20 @@ def test_file_adjoint_errors(snp_files, tmp_path):
         g.stream_backward_file(u8, m, *z, fmt=torch.uint8, col0=m + 1)
     assert g.stream_backward_file(u8, m, *z, fmt=torch.uint8, col0=m).blocks == 0
     g.close()
+
+
+@pytest.mark.parametrize("fmt", [torch.float64, "u2"])
+def test_stream_grad_file_equals_stream_grad(snp_files, fmt):
+    """The whole file pipeline (forward from the file, the loss's cotangents,
+    the adjoint from the file) against stream_grad on the same SNPs in memory,
+    in refined FP32 x2: bitwise equal outputs and gradients."""
+    Phi, h2, XL, y, XR, f64, u8, u2 = snp_files
+    args = (_t(Phi), h2, _t(XL), _t(y))
+    kw = dict(block_cols=2048, precision="fp32_ir", refine_sweeps=2)
+    loss, gy, gh, outs = stream_grad(*args, torch.tensor(XR).pin_memory(), t2_loss, **kw)
+    path, off = (f64, 24) if fmt is torch.float64 else (u2, 0)
+    lf, fy, fh, fouts = stream_grad_file(*args, path, XR.shape[0], t2_loss, fmt=fmt, offset=off, **kw)
+    assert lf == loss and float(fh) == float(gh)
+    assert np.array_equal(fy.cpu().numpy(), gy.cpu().numpy())
+    for a, b in zip(fouts, outs):
+        assert np.array_equal(a.numpy(), b.numpy(), equal_nan=True)
