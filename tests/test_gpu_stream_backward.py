@@ -4,7 +4,7 @@ over SNP blocks held in page-locked host memory, then gls_backward_finish.
 - Against the FP64 CPU autograd reference of Eq. 1 (loss sum_i t_i^2): every
   entry of the y and X_R gradients within 1e-8 element-wise (floor one
   millionth of the largest entry), the h2 gradient relative 1e-8; in FP64 and
-  refined FP32.
+  refined FP32, with p = 4, 3 and 1 (no covariates).
 - Bitwise equal to the device-resident adjoint (GLSFunction, gls_backward_block
   per block), with and without the opening ramp of short blocks (every block
   but the last a multiple of 16 SNPs), when resumed with col0, in serial mode
@@ -68,7 +68,7 @@ def _cotangents(Phi, h2, XL, y, XR_host, bc, precision, sweeps, **kw):
 
 
 @pytest.mark.parametrize("precision,sweeps", [("fp64", 0), ("fp32_ir", 2)])
-@pytest.mark.parametrize("n,p,m,bc,h2", [(300, 4, 700, 128, 0.3), (257, 3, 333, 100, 0.6)])
+@pytest.mark.parametrize("n,p,m,bc,h2", [(300, 4, 700, 128, 0.3), (257, 3, 333, 100, 0.6), (200, 1, 150, 64, 0.45)])
 def test_streamed_adjoint_matches_reference(n, p, m, bc, h2, precision, sweeps):
     Phi, h2, XL, y, XR = _problem(n, p, m, seed=n + m, h2=h2)
     loss, gy, gX, gh, _ = _streamed(Phi, h2, XL, y, XR, bc, precision, sweeps)
